@@ -1,0 +1,235 @@
+"""CPU oracle for parallel multicanonical sampling -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never calls it and shares no code
+with it.
+
+The sampler, table and recursion are plain C loops (``muca_oracle.c``); this
+module wraps them with ctypes and adds, in plain numpy:
+  - the flatness test of the weight iteration (Sec. 3: full range covered and
+    every entry within bounds of the others);
+  - time-series reweighting, Eq. (2), written over energy bins.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import build as _build
+
+ISING, POTTS = 0, 1
+REC_NONE, REC_MUCA, REC_PROD = 0, 1, 2
+TCOLS = 9
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build()
+        L = ctypes.CDLL(path)
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C")
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+        c_int, c_u64, c_u32, c_dbl = ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_energy.argtypes = [c_int, c_int, u8p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.orc_reachable.argtypes = [c_int, c_int, c_int, u8p]
+        L.orc_bruteforce.argtypes = [c_int, c_int, c_int, i64p, i64p]
+        L.orc_bruteforce_canonical.argtypes = [c_int, c_int, c_int, c_dbl,
+                                               ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]
+        L.orc_init.argtypes = [c_int, c_int, c_int, c_int, c_u64, u8p, i32p, i32p]
+        L.orc_build_table.argtypes = [c_int, f64p, u32p]
+        L.orc_sweeps.argtypes = [c_int, c_int, c_int, c_int, c_u64, c_u32, c_int, c_int, u32p, u8p,
+                                 i32p, i32p, i32p, i64p, c_int]
+        L.orc_merge.argtypes = [c_int, c_int, i32p, i64p]
+        L.orc_recursion.argtypes = [c_int, i64p, f64p]
+        for f in ("orc_philox4x32_10", "orc_energy", "orc_reachable", "orc_bruteforce",
+                  "orc_bruteforce_canonical", "orc_init", "orc_build_table", "orc_sweeps",
+                  "orc_merge", "orc_recursion"):
+            getattr(L, f).restype = None
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# ------------------------------------------------------------------ primitives
+
+def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def energy(model: int, L: int, spins: np.ndarray):
+    k, m = ctypes.c_int32(), ctypes.c_int32()
+    lib().orc_energy(model, L, np.ascontiguousarray(spins, np.uint8), ctypes.byref(k), ctypes.byref(m))
+    return k.value, m.value
+
+
+def reachable(model: int, q: int, L: int) -> np.ndarray:
+    mask = np.zeros(2 * L * L + 1, np.uint8)
+    lib().orc_reachable(model, q, L, mask)
+    return mask.astype(bool)
+
+
+def bruteforce(model: int, q: int, L: int):
+    """Exact Omega(k) and sum of |M| per k by enumerating all states."""
+    nb = 2 * L * L + 1
+    om, sm = np.zeros(nb, np.int64), np.zeros(nb, np.int64)
+    lib().orc_bruteforce(model, q, L, om, sm)
+    return om, sm
+
+
+def bruteforce_canonical(model: int, q: int, L: int, beta: float):
+    e, e2, am = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_bruteforce_canonical(model, q, L, beta, ctypes.byref(e), ctypes.byref(e2), ctypes.byref(am))
+    return e.value, e2.value, am.value
+
+
+def build_table(lnW: np.ndarray) -> np.ndarray:
+    lnW = np.ascontiguousarray(lnW, np.float64)
+    T = np.zeros((lnW.size, TCOLS), np.uint32)
+    lib().orc_build_table(lnW.size, lnW, T)
+    return T
+
+
+def energies(model: int, L: int) -> np.ndarray:
+    """E of every bin k: Ising E = -2N + 2k (Eq. 3), Potts E = -2N + k (Eq. 4)."""
+    N = L * L
+    k = np.arange(2 * N + 1, dtype=np.float64)
+    return -2.0 * N + (2.0 * k if model == ISING else k)
+
+
+# ------------------------------------------------------------------ flatness
+
+@dataclass
+class Flatness:
+    covered: bool
+    flat: bool
+    min_over_max: float
+    min_over_avg: float
+    max_over_avg: float
+    k_lo: int
+    k_hi: int
+    visited: int
+    reachable: int
+
+
+def flatness(H: np.ndarray, mask: np.ndarray, ratio: float = 0.5, rule: int = 0) -> Flatness:
+    """Flatness over the reachable bins.  rule 0: every reachable bin visited
+    and min/max >= ratio.  rule 1 (the paper's, Sec. 3): every reachable bin
+    visited and every entry within [avg/2, 2 avg]."""
+    h = H[mask].astype(np.float64)
+    nz = np.nonzero(H > 0)[0]
+    covered = bool(np.all(h > 0))
+    hmax, hmin, havg = float(h.max()), float(h.min()), float(h.mean())
+    mom = hmin / hmax if hmax > 0 else 0.0
+    if rule == 0:
+        flat = covered and mom >= ratio
+    else:
+        flat = covered and bool(np.all(h >= 0.5 * havg)) and bool(np.all(h <= 2.0 * havg))
+    return Flatness(covered, flat, mom, hmin / havg if havg > 0 else 0.0,
+                    hmax / havg if havg > 0 else 0.0,
+                    int(nz[0]) if nz.size else -1, int(nz[-1]) if nz.size else -1,
+                    int(nz.size), int(mask.sum()))
+
+
+# ------------------------------------------------------------------ run state
+
+class OracleRun:
+    """One MUCA problem on the CPU: spins, per-chain state, lnW and T."""
+
+    def __init__(self, model: int, L: int, n_chains: int, seed: int, q: int = 2,
+                 n_threads: Optional[int] = None, chains: Optional[np.ndarray] = None):
+        self.model, self.L, self.q, self.seed = model, L, q if model == POTTS else 2, seed
+        self.N = L * L
+        self.n_bins = 2 * self.N + 1
+        self.n_chains = n_chains
+        self.n_threads = n_threads or default_threads()
+        self.spins = np.zeros((n_chains, self.N), np.uint8)
+        self.k = np.zeros(n_chains, np.int32)
+        self.m = np.zeros(n_chains, np.int32)
+        lib().orc_init(model, self.q, L, n_chains, seed, self.spins, self.k, self.m)
+        self.lnW = np.zeros(self.n_bins, np.float64)
+        self.T = build_table(self.lnW)
+        self.hist = np.zeros((n_chains, self.n_bins), np.int32)
+        self.sabs = np.zeros((n_chains, self.n_bins), np.int64)
+        self.sweep = 0
+        self.mask = reachable(model, self.q, L)
+
+    def set_log_weights(self, lnW: np.ndarray):
+        self.lnW = np.array(lnW, np.float64)
+        self.T = build_table(self.lnW)
+
+    def sweeps(self, n: int, record: int):
+        lib().orc_sweeps(self.model, self.q, self.L, self.n_chains, self.seed, self.sweep, n, record,
+                         self.T, self.spins, self.k, self.m, self.hist, self.sabs, self.n_threads)
+        self.sweep += n
+
+    def merged(self) -> np.ndarray:
+        H = np.zeros(self.n_bins, np.int64)
+        lib().orc_merge(self.n_chains, self.n_bins, self.hist, H)
+        return H
+
+    def iterate(self, n_sweeps: int, ratio: float = 0.5, rule: int = 0):
+        """One weight iteration: sweeps with histograms, merge, flatness on
+        the merged histogram, recursion, new table, cleared histograms."""
+        self.hist[:] = 0
+        self.sweeps(n_sweeps, REC_MUCA)
+        H = self.merged()
+        fl = flatness(H, self.mask, ratio, rule)
+        per_chain = self.hist.copy()
+        lib().orc_recursion(self.n_bins, H, self.lnW)
+        self.T = build_table(self.lnW)
+        self.hist[:] = 0
+        return H, fl, per_chain
+
+    def production(self, n_therm: int, n_prod: int):
+        self.sweeps(n_therm, REC_NONE)
+        self.hist[:] = 0
+        self.sabs[:] = 0
+        self.sweeps(n_prod, REC_PROD)
+        cnt = self.hist.astype(np.int64).sum(axis=0)
+        sab = self.sabs.sum(axis=0)
+        return cnt, sab
+
+
+# ------------------------------------------------------------------ reweighting
+
+def reweight(model: int, L: int, lnW: np.ndarray, cnt: np.ndarray, sabs: np.ndarray,
+             betas: Sequence[float]):
+    """Time-series reweighting, Eq. (2), grouped by energy bin.
+
+    Every measurement in bin k carries weight exp(-beta E_k) / W(E_k); a bin
+    with cnt_k measurements and |M| sum S_k contributes cnt_k and S_k times
+    that weight.  Returns <E>/N, C_V = beta^2 (<E^2> - <E>^2) / N (the
+    specific heat of Sec. 5) and <|M|>/N, all in float64.
+    """
+    N = L * L
+    E = energies(model, L)
+    sel = cnt > 0
+    Ek, lw = E[sel], np.asarray(lnW, np.float64)[sel]
+    ck, sk = cnt[sel].astype(np.float64), sabs[sel].astype(np.float64)
+    e_out, c_out, m_out = [], [], []
+    for beta in betas:
+        a = np.log(ck) - lw - beta * Ek
+        A = a.max()
+        w = np.exp(a - A)
+        Z = w.sum()
+        em = (w * Ek).sum() / Z
+        var = (w * (Ek - em) ** 2).sum() / Z
+        # |M| sums carry the same per-measurement weight exp(-lnW - beta E)
+        am = (sk * np.exp(-lw - beta * Ek - A)).sum() / Z
+        e_out.append(em / N)
+        c_out.append(beta * beta * var / N)
+        m_out.append(am / N)
+    return np.array(e_out), np.array(c_out), np.array(m_out)

@@ -1,0 +1,269 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against a closed form, an independent
+implementation, brute force, or an invariant the method must satisfy, chosen
+so that a plausible mistake (a dropped term, a wrong sign or index, a
+transposed operand, a wrong boundary) fails at least one of them.
+"""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import exact_ising
+
+ISING, POTTS = oracle.ISING, oracle.POTTS
+
+
+# ------------------------------------------------------------------ Philox
+
+def _torch_philox_binary(tmp_path_factory):
+    import torch.utils.cpp_extension as ce
+    src = os.path.join(os.path.dirname(__file__), "native", "philox_torch_pin.cpp")
+    exe = str(tmp_path_factory.mktemp("ptp") / "ptp")
+    inc = []
+    for p in ce.include_paths():
+        inc += ["-I", p]
+    subprocess.check_call(["g++", "-O1", "-std=c++17", *inc, src, "-o", exe])
+    return exe
+
+
+def test_philox_matches_independent_implementation(tmp_path_factory):
+    """Philox4x32-10 against PyTorch's header implementation of the same
+    published generator (Salmon et al., SC'11), on edge and random counters."""
+    exe = _torch_philox_binary(tmp_path_factory)
+    rng = np.random.default_rng(12345)
+    cases = [(0, 0, 0, 0, 0, 0), (2**32 - 1,) * 6, (1, 2, 3, 4, 5, 6)]
+    cases += [tuple(int(v) for v in rng.integers(0, 2**32, 6)) for _ in range(300)]
+    inp = "\n".join(" ".join(str(v) for v in c) for c in cases) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        ref = [int(v) for v in line.split()]
+        got = [int(v) for v in oracle.philox(c[:4], c[4:])]
+        assert got == ref, (c, got, ref)
+
+
+def test_philox_output_bits_are_balanced():
+    """Every output bit of consecutive counters is 1 about half the time."""
+    words = np.array([oracle.philox((i, 7, 3, 0), (1, 0)) for i in range(4096)], np.uint32).ravel()
+    bits = ((words[:, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(axis=0)
+    assert np.all(np.abs(bits - 0.5) < 5 * 0.5 / math.sqrt(words.size))
+
+
+# ------------------------------------------------------------------ exact DOS
+
+def test_bruteforce_ising_L4_equals_kaufman_beale():
+    om, _ = oracle.bruteforce(ISING, 2, 4)
+    assert list(om) == list(exact_ising.density_of_states(4))
+
+
+def test_bruteforce_ising_canonical_equals_kaufman():
+    """<E> and C_V from summing all 2^16 states equal derivatives of
+    Kaufman's ln Z (an independent closed form)."""
+    for beta in (0.1, 0.3, 0.4407, 0.6):
+        e, e2, _ = oracle.bruteforce_canonical(ISING, 2, 4, beta)
+        ek, cvk = exact_ising.kaufman_energy_cv(4, beta)
+        assert e / 16 == pytest.approx(ek, rel=1e-9)
+        assert beta * beta * (e2 - e * e) / 16 == pytest.approx(cvk, rel=1e-8)
+
+
+@pytest.mark.parametrize("L", [4, 6, 8])
+def test_beale_invariants_and_reachable_mask(L):
+    """Exact Omega: total 2^N, symmetric in k <-> 2N-k, Omega(0) = 2,
+    Omega(4) = 2N (one flipped spin), Omega(6) = 4N (two adjacent flipped);
+    its support is exactly the oracle's reachable mask."""
+    N = L * L
+    om = np.array([float(v) for v in exact_ising.density_of_states(L)])
+    omi = exact_ising.density_of_states(L)
+    assert sum(omi) == 2**N
+    assert omi[0] == 2 and omi[4] == 2 * N and omi[6] == 4 * N
+    assert all(omi[k] == omi[2 * N - k] for k in range(2 * N + 1))
+    assert np.array_equal(om > 0, oracle.reachable(ISING, 2, L))
+
+
+@pytest.fixture(scope="module")
+def potts_l3():
+    return oracle.bruteforce(POTTS, 8, 3)
+
+
+def test_bruteforce_potts_L3_closed_forms(potts_l3):
+    """8-Potts on the 3x3 torus: total 8^9; Omega(0) = q (uniform states);
+    Omega(4) = q(q-1)N (one odd site); Omega(6) = q(q-1)(2N + 2L) (an
+    adjacent pair, or a full row/column on the L = 3 torus); Omega(7) =
+    q(q-1)(q-2) 2N (an adjacent pair of two different odd colours)."""
+    om, _ = potts_l3
+    q, N, L = 8, 9, 3
+    assert om.sum() == q**N
+    assert om[0] == q
+    assert om[4] == q * (q - 1) * N
+    assert om[6] == q * (q - 1) * (2 * N + 2 * L)
+    assert om[7] == q * (q - 1) * (q - 2) * 2 * N
+    assert np.array_equal(om > 0, oracle.reachable(POTTS, 8, 3))
+
+
+def test_ising_equals_two_state_potts():
+    """The Ising model is the q = 2 Potts model (Sec. 3): both count k the
+    same way, so brute-force Omega(k) agrees."""
+    om_i, _ = oracle.bruteforce(ISING, 2, 4)
+    om_p, _ = oracle.bruteforce(POTTS, 2, 4)
+    assert np.array_equal(om_i, om_p)
+
+
+# ------------------------------------------------------------------ table
+
+def test_table_properties():
+    rng = np.random.default_rng(7)
+    lnW = np.cumsum(rng.normal(0, 3, 129))
+    T = oracle.build_table(lnW)
+    n = lnW.size
+    for k in range(n):
+        for dk in range(-4, 5):
+            t = k + dk
+            v = int(T[k, dk + 4])
+            if t < 0 or t >= n:
+                assert v == 0
+                continue
+            d = lnW[t] - lnW[k]
+            if d >= 0:
+                assert v == 0xFFFFFFFF
+            else:
+                p = math.exp(d)
+                # floor(2^32 p): within one unit of 2^32 p, never above it
+                assert v <= p * 2**32 + 1e-6 and v > p * 2**32 - 1 - 1e-6 or v == 0xFFFFFFFF
+    # dk = 0 always accepts
+    assert np.all(T[:, 4] == 0xFFFFFFFF)
+
+
+def test_table_monotone_in_weight_difference():
+    d = np.linspace(-30, 1, 4001)
+    lnW = np.stack([np.zeros_like(d), d], axis=1)
+    vals = []
+    for row in lnW:
+        T = oracle.build_table(row)
+        vals.append(int(T[0, 5]))
+    assert all(a <= b for a, b in zip(vals, vals[1:]))
+    assert vals[0] == 0 and vals[-1] == 0xFFFFFFFF
+
+
+# ------------------------------------------------------------------ sampler
+
+@pytest.mark.parametrize("model,L,q", [(ISING, 4, 2), (ISING, 6, 2), (POTTS, 3, 8), (POTTS, 5, 8)])
+def test_tracked_state_and_histogram_invariants(model, L, q):
+    """Tracked k and M equal a full recompute from the spins; each chain
+    adds exactly one count per recorded sweep; unreachable bins stay empty."""
+    r = oracle.OracleRun(model, L, 37, 99, q=q, n_threads=3)
+    rng = np.random.default_rng(1)
+    r.set_log_weights(np.cumsum(rng.normal(0, 0.7, r.n_bins)))
+    r.sweeps(5, oracle.REC_NONE)
+    r.hist[:] = 0
+    r.sweeps(40, oracle.REC_MUCA)
+    for c in range(r.n_chains):
+        k, m = oracle.energy(model, L, r.spins[c])
+        assert (k, m) == (r.k[c], r.m[c])
+    assert np.all(r.hist.sum(axis=1) == 40)
+    assert np.all(r.merged()[~r.mask] == 0)
+    assert np.all(r.spins < q)
+
+
+@pytest.mark.parametrize("model,q", [(ISING, 2), (POTTS, 8)])
+def test_infinite_temperature_moves(model, q):
+    """With lnW = 0 every move is accepted: after one sweep every site has
+    changed, and the Potts offset (s' - s - 1) mod q is uniform on 0..q-2."""
+    r = oracle.OracleRun(model, 6, 400, 5, q=q)
+    before = r.spins.copy()
+    r.sweeps(1, oracle.REC_NONE)
+    assert np.all(r.spins != before)
+    if model == POTTS:
+        off = ((r.spins.astype(int) - before.astype(int) - 1) % q).ravel()
+        assert off.max() == q - 2
+        cnt = np.bincount(off, minlength=q - 1)
+        assert stats.chisquare(cnt).pvalue > 1e-3
+
+
+def test_initial_spins_are_uniform():
+    r = oracle.OracleRun(POTTS, 16, 64, 3, q=8)
+    cnt = np.bincount(r.spins.ravel(), minlength=8)
+    assert stats.chisquare(cnt).pvalue > 1e-3
+    r = oracle.OracleRun(ISING, 16, 64, 3)
+    assert abs(r.spins.mean() - 0.5) < 5 * 0.5 / math.sqrt(r.spins.size)
+
+
+def _chisq(obs, exp_p):
+    n = obs.sum()
+    e = exp_p * n
+    keep = e >= 5
+    o2 = np.append(obs[keep], obs[~keep].sum())
+    e2 = np.append(e[keep], e[~keep].sum())
+    if e2[-1] == 0:
+        o2, e2 = o2[:-1], e2[:-1]
+    return stats.chisquare(o2, e2).pvalue
+
+
+@pytest.mark.parametrize("model,L,q,beta", [(ISING, 4, 2, 0.3), (ISING, 4, 2, 0.45), (POTTS, 3, 8, 1.0)])
+def test_canonical_limit_chi_square(model, L, q, beta, potts_l3):
+    """lnW = -beta E turns the multicanonical chain into canonical Metropolis,
+    Eq. (1) with W = exp(-beta E).  One end-of-run sample per chain (chains
+    are independent) must follow Omega(E) exp(-beta E) / Z exactly."""
+    if model == ISING:
+        om, _ = oracle.bruteforce(ISING, 2, L)
+    else:
+        om, _ = potts_l3
+    E = oracle.energies(model, L)
+    r = oracle.OracleRun(model, L, 20000, 11, q=q)
+    r.set_log_weights(-beta * E)
+    r.sweeps(40, oracle.REC_NONE)
+    r.hist[:] = 0
+    r.sweeps(1, oracle.REC_MUCA)
+    obs = r.merged().astype(np.float64)
+    w = om * np.exp(-beta * (E - E.min()))
+    p = w / w.sum()
+    assert _chisq(obs, p) > 1e-3
+
+
+def test_muca_converges_to_exact_dos_ising_L4():
+    """Iterating W <- W/H to a flat histogram gives lnW = -ln Omega + const
+    (Sec. 2: W = 1/Omega makes every energy equally likely)."""
+    r = oracle.OracleRun(ISING, 4, 64, 21)
+    flat = False
+    for _ in range(40):
+        _, fl, _ = r.iterate(2000)
+        flat = flat or fl.flat
+    assert flat
+    lo = np.log(np.array(exact_ising.density_of_states(4), np.float64), where=r.mask,
+                out=np.full(r.n_bins, -np.inf))
+    d = (-r.lnW - lo)[r.mask]
+    d -= d.mean()
+    assert np.abs(d).max() < 0.1
+
+
+def test_muca_converges_to_exact_dos_potts_L3(potts_l3):
+    om, _ = potts_l3
+    r = oracle.OracleRun(POTTS, 3, 64, 22, q=8)
+    flat = False
+    for _ in range(40):
+        _, fl, _ = r.iterate(2000)
+        flat = flat or fl.flat
+    assert flat
+    lo = np.log(om.astype(np.float64), where=r.mask, out=np.full(r.n_bins, -np.inf))
+    d = (-r.lnW - lo)[r.mask]
+    d -= d.mean()
+    assert np.abs(d).max() < 0.15
+
+
+def test_small_ising_run_reaches_exact_dos_L8():
+    """The Ising L = 8 run with 4 chains and 20 iterations of 1e4 sweeps
+    becomes flat and its weights match Beale's exact ln Omega."""
+    r = oracle.OracleRun(ISING, 8, 4, 1)
+    flats = []
+    for _ in range(20):
+        _, fl, _ = r.iterate(10_000)
+        flats.append(fl.flat)
+    assert flats[-1] and sum(flats) >= 8
+    lo = exact_ising.log_dos(8)
+    d = (-r.lnW - lo)[r.mask]
+    d -= d.mean()
+    assert np.abs(d).max() < 0.35 and d.std() < 0.1
