@@ -1,0 +1,152 @@
+"""Benchmark: spin-update throughput of the multicanonical weight iteration.
+
+One step is one weight iteration of the 2D Ising L = 64 workload with 4096
+chains: 2000 recorded sweeps of every chain (the sweep kernel), the merge of
+the per-chain histograms, the recursion lnW <- lnW - ln H and the rebuilt
+acceptance tables.  Inputs (spins, tables) are resident in HBM before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-update attempts/s (G/s) + %roofline; sweeps-to-flat, learned vs plain"
+
+# Integer lane operations one Ising update needs by the algorithm (not by
+# this kernel's instruction count): a quarter of a Philox4x32-10 block
+# (10 rounds x (2 low + 2 high products + 4 xors) = 80 ops / 4 sites = 20)
+# plus the update itself (4 neighbour compares, 3 adds, 2 for the table
+# index, 1 compare, 2 for the accepted state) = 12.
+OPS_PER_ISING_UPDATE = 32
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one int32 op per lane per cycle.
+PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("muca_kernels.hip", "muca_device.h"):
+        with open(os.path.join(ROOT, "paper_1212_3975_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(updates_per_launch: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "sweep_ising64_c4096_pmc.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    per_update = d.get("hbm_bytes_per_update")
+    return None if per_update is None else per_update * updates_per_launch
+
+
+def cpu_baseline(prob, sweeps: int, n_chains: int):
+    """The oracle as it stands, on the host cores, on a bounded sample of the
+    same workload: n_chains chains for `sweeps` sweeps."""
+    import oracle
+    threads = oracle.default_threads()
+    orc = oracle.OracleRun(prob.model, prob.L, n_chains, prob.seed, q=prob.q, n_threads=threads)
+    t0 = time.perf_counter()
+    orc.sweeps(sweeps, oracle.REC_MUCA)
+    dt = time.perf_counter() - t0
+    ups = n_chains * sweeps * prob.N / dt
+    return {"value": round(ups / 1e9, 4), "unit": "G/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_chains} chains x {sweeps} recorded sweeps of Ising L={prob.L} "
+                      f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rng-mode", type=int, default=0)
+    ap.add_argument("--chains-per-wg", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by chains "
+              "with one histogram all-reduce per iteration, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1212_3975_amd as pm
+    from workloads import C2
+
+    prob = C2.problems[0]
+    M = C2.sweeps_per_iter
+    torch.cuda.set_device(0)
+    ctx = pm.Muca([prob], device="cuda:0", rng_mode=args.rng_mode, chains_per_wg=args.chains_per_wg)
+    launch = ctx.launch_info()
+    updates_per_step = prob.n_chains * prob.N * M
+
+    for _ in range(args.warmup):
+        ctx.sweep(M, pm.REC_MUCA)
+        ctx.merge_update(True)
+    ctx.sweep_timing()   # reset kernel timing to the timed region
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        ctx.sweep(M, pm.REC_MUCA)
+        stats = ctx.merge_update(True)[0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    avg_ms, n_launch = ctx.sweep_timing()
+
+    value = updates_per_step * args.steps / dt / 1e9
+    achieved = OPS_PER_ISING_UPDATE * updates_per_step / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    kernel_rate = updates_per_step / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    # production and reweighting leg (reported, not part of the value)
+    ctx.clear_production()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    ctx.sweep(200, pm.REC_PROD)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - tp
+    tr = time.perf_counter()
+    ctx.reweight(0, C2.betas)
+    tr = time.perf_counter() - tr
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "G/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "2D Ising L=64 periodic, 4096 chains, one weight iteration of 2000 sweeps "
+                               "(sweep + merge + recursion + tables)",
+                   "L": prob.L, "chains": prob.n_chains, "sweeps_per_iter": M, "seed": prob.seed,
+                   "launch": launch},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_INT32_OPS / 1e12, 2),
+                     "unit": "Tops/s (int32 lane ops)", "frac": round(achieved / PEAK_INT32_OPS, 5),
+                     "traffic": measured_traffic(updates_per_step),
+                     "kernel": "sweep_kernel", "kernel_avg_ms": round(avg_ms, 3), "kernel_launches": n_launch,
+                     "kernel_rate_Gups": round(kernel_rate, 3), "ops_per_update": OPS_PER_ISING_UPDATE},
+        "extra": {"production_Gups": round(prob.n_chains * prob.N * 200 / tp / 1e9, 3),
+                  "reweight_ms_200_betas": round(tr * 1e3, 3),
+                  "last_iter": {k: stats[k] for k in ("k_lo", "k_hi", "visited", "reachable", "flat")},
+                  "kernel_source_hash": kernel_source_hash()},
+    }
+    ctx.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, 2000, 128)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * muca.h -- C ABI of the MI355X multicanonical (MUCA) sampling library.
+ *
+ * The method (Zierenberg, Marenz, Janke, "Scaling properties of a parallel
+ * implementation of the multicanonical algorithm"):
+ *   - Sec. 2, Eq. (1): sample with weights W(E) instead of exp(-beta E); with
+ *     W = 1/Omega the energy histogram is flat;
+ *   - Sec. 2: the weights are found iteratively, W <- W / H, kept in logs;
+ *   - Sec. 2, "Parallel Version": p independent chains share W, each fills its
+ *     own histogram H_i, the histograms are summed, the new W is sent back;
+ *   - Sec. 3, Eqs. (3)-(4): 2D Ising and q-state Potts models on an L x L
+ *     periodic square lattice, sweeps of V = L^2 single-spin updates, a start
+ *     at infinite temperature, updates only where H > 0;
+ *   - Sec. 2, Eq. (2): time-series reweighting of production data.
+ *
+ * Conventions of this library (fixed where the paper is silent):
+ *   - N = L*L.  Energies are binned by k = number of unsatisfied bonds,
+ *     k = 0..2N, so there are 2N+1 bins; Ising E = -2N + 2k, Potts E = -2N + k.
+ *   - Random numbers: Philox4x32-10, key = (seed & 0xffffffff, seed >> 32),
+ *     counter = (site block, sweep, chain, stream).  Init draws word 0 of
+ *     counter (site, 0, chain, 1).  Sweep s, site i: Ising uses word (i & 3)
+ *     of counter (i >> 2, s, chain, 0); Potts uses words 2(i&1) (proposal)
+ *     and 2(i&1)+1 (acceptance) of counter (i >> 1, s, chain, 0).
+ *   - Sites are updated in order i = y*L + x, x fastest.  The Potts proposal
+ *     is s' = (s + 1 + ((r * (q-1)) >> 32)) mod q (uniform over the q-1 other
+ *     states).  A move with change dk is accepted iff T[k][dk] == 0xffffffff
+ *     or u < T[k][dk], where T[k][dk] = floor(2^32 min(1, exp(lnW[k+dk] -
+ *     lnW[k]))) and values >= 2^32 - 1 are stored as 0xffffffff.
+ *   - Every chain adds one count to its histogram at the end of each
+ *     recorded sweep.  The recursion is lnW[k] -= log(H[k]) where H[k] > 0,
+ *     with no renormalisation.  The host evaluates log/exp with the C library
+ *     in IEEE double, so histograms, weights and tables are reproducible bit
+ *     for bit by any implementation of the same definitions.
+ *
+ * Errors: every call returns a muca_status; nothing throws across the ABI.
+ * MUCA_EINVAL for bad arguments, MUCA_ENOMEM for a workspace that is too
+ * small, MUCA_EHIP for a failed HIP call (text in mucaLastError), MUCA_ESTATE
+ * for a call in the wrong state.  A context is not thread-safe.
+ */
+#ifndef MUCA_H_
+#define MUCA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct muca_ctx_s *muca_ctx;
+
+typedef enum {
+    MUCA_OK = 0,
+    MUCA_EINVAL = -1,
+    MUCA_ENOMEM = -2,
+    MUCA_EHIP = -3,
+    MUCA_ESTATE = -4
+} muca_status;
+
+enum { MUCA_ISING = 0, MUCA_POTTS = 1 };
+enum { MUCA_REC_NONE = 0, MUCA_REC_MUCA = 1, MUCA_REC_PROD = 2 };
+
+/* One problem: a model on one lattice with n_chains chains sharing lnW.
+ * Ising: L even, 4 <= L <= 256, q ignored.  Potts: 3 <= L <= 256, 3 <= q <= 8.
+ * 1 <= n_chains <= 1<<20.  seed keys the generator (Sec. 2: same weights,
+ * different random numbers per chain). */
+typedef struct {
+    int32_t model;
+    int32_t q;
+    int32_t L;
+    int32_t n_chains;
+    uint64_t seed;
+} muca_problem;
+
+/* Launch and iteration options; zero means "default / autotune".
+ *   chains_per_wg    chains handled by one workgroup (16, 32 or 64; 0 = tune)
+ *   rng_mode         0 = tune, 1 = walker draws its own numbers,
+ *                    2 = helper waves of the workgroup draw them
+ *   spin_placement   0 = tune, 1 = lattice in LDS, 2 = lattice in HBM
+ *   table_placement  0 = tune, 1 = table in LDS, 2 = table in HBM
+ *   use_graph        1 = mucaIterate replays one HIP graph per iteration
+ *   production       1 = reserve production accumulators (|M| sums)
+ *   flat_ratio       min/max threshold of the flatness test (default 0.5)
+ *   flat_rule        0 = all reachable bins visited and min/max >= flat_ratio;
+ *                    1 = all reachable bins visited and every entry within
+ *                        [avg/2, 2 avg] (the rule of Sec. 3)
+ *   tune_sweeps      sweeps per timed candidate when tuning (default 4) */
+typedef struct {
+    int32_t chains_per_wg;
+    int32_t rng_mode;
+    int32_t spin_placement;
+    int32_t table_placement;
+    int32_t use_graph;
+    int32_t production;
+    double flat_ratio;
+    int32_t flat_rule;
+    int32_t tune_sweeps;
+} muca_options;
+
+/* Statistics of one weight iteration for one problem, from the merged
+ * histogram H of that iteration (before the recursion is applied). */
+typedef struct {
+    int32_t k_lo, k_hi;       /* smallest / largest k with H > 0 */
+    int32_t visited;          /* bins with H > 0 */
+    int32_t reachable;        /* bins that can occur at all */
+    int32_t covered;          /* every reachable bin has H > 0 */
+    int32_t flat;             /* covered and the flatness rule holds */
+    double min_over_max, min_over_avg, max_over_avg;  /* over reachable bins */
+    int64_t total;            /* sum of H = chains * recorded sweeps */
+} muca_iter_stats;
+
+/* Selected launch configuration of one problem (after tuning). */
+typedef struct {
+    int32_t chains_per_wg, rng_mode, spin_placement, table_placement;
+    int32_t lds_bytes, n_workgroups, pad0, pad1;
+} muca_launch_info;
+
+/* Bytes of device workspace that mucaInit needs for these problems. */
+muca_status mucaWorkspaceSize(const muca_problem *problems, int32_t n_problems,
+                              const muca_options *opts, size_t *bytes);
+
+/* Creates a context.  d_workspace: device memory of at least the size from
+ * mucaWorkspaceSize, owned by the caller, must outlive the context.
+ * hip_stream: the hipStream_t every call enqueues on (NULL = default stream).
+ * Draws the initial spins (Sec. 3, infinite temperature), computes k and M,
+ * sets lnW = 0, builds the tables and, if asked, tunes the launch. */
+muca_status mucaInit(muca_ctx *out, const muca_problem *problems, int32_t n_problems,
+                     const muca_options *opts, void *d_workspace, size_t ws_bytes,
+                     void *hip_stream);
+
+/* Replaces lnW of problem prob (n_bins = 2N+1 host doubles, copied) and
+ * rebuilds its table. */
+muca_status mucaSetLogWeights(muca_ctx ctx, int32_t prob, const double *lnW, int32_t n_bins);
+
+/* Runs n_sweeps sweeps of every chain of every problem (Sec. 3), asynchronously
+ * on the stream.  record: MUCA_REC_NONE (thermalisation), MUCA_REC_MUCA
+ * (one histogram count per chain per sweep), MUCA_REC_PROD (count and |M|
+ * per chain per sweep). */
+muca_status mucaSweep(muca_ctx ctx, int64_t n_sweeps, int32_t record);
+
+/* Merges the per-chain histograms (H = sum_i H_i, Sec. 2) and clears them.
+ * update = 1 also applies lnW <- lnW - ln H where H > 0 and rebuilds the
+ * tables.  Writes one muca_iter_stats per problem to out (may be NULL).
+ * Synchronises the stream. */
+muca_status mucaMergeUpdate(muca_ctx ctx, int32_t update, muca_iter_stats *out);
+
+/* One weight iteration: n_sweeps recorded sweeps, merge, recursion, new
+ * tables (Fig. 1's loop body).  With use_graph the whole iteration is one
+ * HIP graph launch.  Synchronises the stream; out as in mucaMergeUpdate. */
+muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out);
+
+/* Time-series reweighting, Eq. (2), of the production data of problem prob
+ * (accumulated by MUCA_REC_PROD sweeps since the last mucaClearProduction)
+ * to n_betas inverse temperatures.  Outputs (host arrays of n_betas doubles,
+ * caller-owned): <E>/N, C_V = beta^2 (<E^2> - <E>^2)/N and <|M|>/N (Ising;
+ * NaN for Potts).  Runs on the device in double precision; synchronises. */
+muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_t n_betas,
+                         double *e_per_site, double *c_v, double *abs_m_per_site);
+
+/* Zeroes the per-chain production accumulators of every problem. */
+muca_status mucaClearProduction(muca_ctx ctx);
+
+/* Copies state of problem prob to host memory (bytes must match exactly):
+ *   MUCA_GET_H        int64[2N+1]      merged histogram of the last merge
+ *   MUCA_GET_LNW      double[2N+1]     current log-weights
+ *   MUCA_GET_T        uint32[2N+1][9]  table, column dk+4, dk = -4..4
+ *                                      (targets outside 0..2N hold 0)
+ *   MUCA_GET_SPINS    uint8[N][C]      spins, site-major, chain fastest
+ *                                      (Ising 0/1 for s = -1/+1, Potts 0..q-1)
+ *   MUCA_GET_K        int32[C]         unsatisfied bonds per chain
+ *   MUCA_GET_M        int32[C]         Ising magnetisation per chain (0 Potts)
+ *   MUCA_GET_CHAIN_H  int32[2N+1][C]   per-chain histograms (not yet merged)
+ *   MUCA_GET_PROD_CNT int64[2N+1]      merged production counts
+ *   MUCA_GET_PROD_ABSM int64[2N+1]     merged production |M| sums
+ *   MUCA_GET_SWEEP    uint32[1]        sweeps done since init
+ *   MUCA_GET_REACH    uint8[2N+1]      reachable-bin mask
+ * Synchronises the stream. */
+enum {
+    MUCA_GET_H = 0, MUCA_GET_LNW = 1, MUCA_GET_T = 2, MUCA_GET_SPINS = 3, MUCA_GET_K = 4,
+    MUCA_GET_M = 5, MUCA_GET_CHAIN_H = 6, MUCA_GET_PROD_CNT = 7, MUCA_GET_PROD_ABSM = 8,
+    MUCA_GET_SWEEP = 9, MUCA_GET_REACH = 10
+};
+muca_status mucaGet(muca_ctx ctx, int32_t what, int32_t prob, void *host_dst, size_t bytes);
+
+/* Launch configuration chosen for problem prob. */
+muca_status mucaLaunchInfo(muca_ctx ctx, int32_t prob, muca_launch_info *info);
+
+/* Average duration in milliseconds of the sweep-kernel launches enqueued by
+ * mucaSweep / mucaIterate since the last call (HIP events on the context's
+ * stream), and how many launches it covers.  Synchronises. */
+muca_status mucaSweepTiming(muca_ctx ctx, double *avg_ms, int32_t *n_launches);
+
+/* Checkpoint of the whole sampling state (spins, k, M, sweep counter, lnW,
+ * per-chain histograms) into a caller-owned host buffer.  With blob == NULL
+ * only *bytes is set.  mucaRestore loads such a blob into a context created
+ * with the same problems; the continued run equals an uninterrupted one bit
+ * for bit.  Both synchronise. */
+muca_status mucaCheckpoint(muca_ctx ctx, void *blob, size_t *bytes);
+muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes);
+
+/* Frees the context (not the workspace).  Safe on NULL. */
+void mucaDestroy(muca_ctx ctx);
+
+/* Last error text of ctx (or of the last failed mucaInit when ctx is NULL). */
+const char *mucaLastError(muca_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MUCA_H_ */

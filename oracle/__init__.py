@@ -43,9 +43,9 @@ def lib():
         L.orc_bruteforce.argtypes = [c_int, c_int, c_int, i64p, i64p]
         L.orc_bruteforce_canonical.argtypes = [c_int, c_int, c_int, c_dbl,
                                                ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]
-        L.orc_init.argtypes = [c_int, c_int, c_int, c_int, c_u64, u8p, i32p, i32p]
+        L.orc_init.argtypes = [c_int, c_int, c_int, c_int, c_int, c_u64, u8p, i32p, i32p]
         L.orc_build_table.argtypes = [c_int, f64p, u32p]
-        L.orc_sweeps.argtypes = [c_int, c_int, c_int, c_int, c_u64, c_u32, c_int, c_int, u32p, u8p,
+        L.orc_sweeps.argtypes = [c_int, c_int, c_int, c_int, c_int, c_u64, c_u32, c_int, c_int, u32p, u8p,
                                  i32p, i32p, i32p, i64p, c_int]
         L.orc_merge.argtypes = [c_int, c_int, i32p, i64p]
         L.orc_recursion.argtypes = [c_int, i64p, f64p]
@@ -149,16 +149,19 @@ class OracleRun:
     """One MUCA problem on the CPU: spins, per-chain state, lnW and T."""
 
     def __init__(self, model: int, L: int, n_chains: int, seed: int, q: int = 2,
-                 n_threads: Optional[int] = None, chains: Optional[np.ndarray] = None):
+                 n_threads: Optional[int] = None, chain0: int = 0):
+        """Chains chain0 .. chain0 + n_chains - 1 of the problem (a chain's
+        trajectory depends only on the seed, its index and lnW)."""
         self.model, self.L, self.q, self.seed = model, L, q if model == POTTS else 2, seed
         self.N = L * L
         self.n_bins = 2 * self.N + 1
         self.n_chains = n_chains
+        self.chain0 = chain0
         self.n_threads = n_threads or default_threads()
         self.spins = np.zeros((n_chains, self.N), np.uint8)
         self.k = np.zeros(n_chains, np.int32)
         self.m = np.zeros(n_chains, np.int32)
-        lib().orc_init(model, self.q, L, n_chains, seed, self.spins, self.k, self.m)
+        lib().orc_init(model, self.q, L, chain0, n_chains, seed, self.spins, self.k, self.m)
         self.lnW = np.zeros(self.n_bins, np.float64)
         self.T = build_table(self.lnW)
         self.hist = np.zeros((n_chains, self.n_bins), np.int32)
@@ -171,7 +174,7 @@ class OracleRun:
         self.T = build_table(self.lnW)
 
     def sweeps(self, n: int, record: int):
-        lib().orc_sweeps(self.model, self.q, self.L, self.n_chains, self.seed, self.sweep, n, record,
+        lib().orc_sweeps(self.model, self.q, self.L, self.chain0, self.n_chains, self.seed, self.sweep, n, record,
                          self.T, self.spins, self.k, self.m, self.hist, self.sabs, self.n_threads)
         self.sweep += n
 

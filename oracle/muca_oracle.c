@@ -211,8 +211,8 @@ void orc_bruteforce_canonical(int model, int q, int L, double beta,
 /* Random spins (beta = 0 start, Sec. 3).  Site i of chain c draws word 0 of
  * the block at counter (i, 0, c, STREAM_INIT).  Ising stores the top bit;
  * Potts maps the word to 0..q-1 by (w * q) >> 32.
- * spins: [n_chains][N] bytes, chain-major. */
-void orc_init(int model, int q, int L, int n_chains, uint64_t seed,
+ * Chains chain0 .. chain0 + n_chains - 1; spins: [n_chains][N] bytes. */
+void orc_init(int model, int q, int L, int chain0, int n_chains, uint64_t seed,
               uint8_t *spins, int32_t *k, int32_t *m)
 {
     int N = L * L;
@@ -220,7 +220,7 @@ void orc_init(int model, int q, int L, int n_chains, uint64_t seed,
         uint8_t *s = spins + (size_t)c * N;
         for (int i = 0; i < N; ++i) {
             uint32_t blk[4];
-            draw_block(seed, (uint32_t)i, 0u, (uint32_t)c, STREAM_INIT, blk);
+            draw_block(seed, (uint32_t)i, 0u, (uint32_t)(chain0 + c), STREAM_INIT, blk);
             if (model == MODEL_ISING)
                 s[i] = (uint8_t)(blk[0] >> 31);
             else
@@ -265,6 +265,7 @@ static int accept(uint32_t u, uint32_t t) { return t == 0xFFFFFFFFu || u < t; }
 
 typedef struct {
     int model, q, L, n_bins;
+    int chain0;              /* generator index of local chain 0 */
     int c_begin, c_end;
     uint64_t seed;
     uint32_t sweep0;
@@ -291,12 +292,12 @@ static void sweep_one_chain(const sweep_job *j, int c, uint32_t sweep)
         uint32_t u;
         if (j->model == MODEL_ISING) {
             /* four sites share one block: site i uses word i mod 4 */
-            if ((i & 3) == 0) draw_block(j->seed, (uint32_t)(i >> 2), sweep, (uint32_t)c, STREAM_SWEEP, blk);
+            if ((i & 3) == 0) draw_block(j->seed, (uint32_t)(i >> 2), sweep, (uint32_t)(j->chain0 + c), STREAM_SWEEP, blk);
             u = blk[i & 3];
             s_new = (uint8_t)(s[i] ^ 1u);
         } else {
             /* two sites share one block: site i uses words 2(i mod 2), 2(i mod 2)+1 */
-            if ((i & 1) == 0) draw_block(j->seed, (uint32_t)(i >> 1), sweep, (uint32_t)c, STREAM_SWEEP, blk);
+            if ((i & 1) == 0) draw_block(j->seed, (uint32_t)(i >> 1), sweep, (uint32_t)(j->chain0 + c), STREAM_SWEEP, blk);
             uint32_t r = blk[2 * (i & 1)];
             u = blk[2 * (i & 1) + 1];
             /* new state uniform over the q-1 others: offset 1 + floor(r (q-1) / 2^32) */
@@ -332,9 +333,10 @@ static void *sweep_worker(void *arg)
     return NULL;
 }
 
-/* n_sweeps sweeps of every chain, sweep numbers sweep0, sweep0+1, ...
- * Chains are independent, so they are split statically over n_threads. */
-void orc_sweeps(int model, int q, int L, int n_chains, uint64_t seed, uint32_t sweep0,
+/* n_sweeps sweeps of chains chain0 .. chain0 + n_chains - 1, sweep numbers
+ * sweep0, sweep0+1, ...  Chains are independent, so they are split
+ * statically over n_threads. */
+void orc_sweeps(int model, int q, int L, int chain0, int n_chains, uint64_t seed, uint32_t sweep0,
                 int n_sweeps, int record, const uint32_t *T, uint8_t *spins, int32_t *k,
                 int32_t *m, int32_t *hist, int64_t *sabs, int n_threads)
 {
@@ -345,7 +347,7 @@ void orc_sweeps(int model, int q, int L, int n_chains, uint64_t seed, uint32_t s
     int per = n_chains / n_threads, rem = n_chains % n_threads, c0 = 0;
     for (int t = 0; t < n_threads; ++t) {
         sweep_job *j = &jobs[t];
-        j->model = model; j->q = q; j->L = L; j->n_bins = 2 * L * L + 1;
+        j->model = model; j->q = q; j->L = L; j->n_bins = 2 * L * L + 1; j->chain0 = chain0;
         j->c_begin = c0; j->c_end = c0 + per + (t < rem ? 1 : 0); c0 = j->c_end;
         j->seed = seed; j->sweep0 = sweep0; j->n_sweeps = n_sweeps; j->record = record;
         j->T = T; j->spins = spins; j->k = k; j->m = m; j->hist = hist; j->sabs = sabs;

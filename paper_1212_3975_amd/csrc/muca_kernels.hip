@@ -1,0 +1,580 @@
+// HIP kernels of the MUCA library for gfx950 (MI355X).
+//
+// Sweep kernel design.  A chain's sweep is strictly sequential (every update
+// reads the chain's current energy bin k), so the only parallelism is across
+// chains: one lane per chain.  A workgroup owns up to 64 chains of one
+// problem.  Its first wave is the walker: lane c runs chain chain0 + c
+// through the sites in order.  Optionally 1..3 more waves are producers:
+// they draw the Philox words of the next chunk of sites for every chain into
+// an LDS double buffer while the walker consumes the current chunk, so the
+// walker issues no multiplies.  The lattice (uint8 per site, chain fastest)
+// and the acceptance table can each live in LDS or in HBM; the host picks
+// the placement per problem.
+#include "muca_device.h"
+
+namespace muca {
+
+// ------------------------------------------------------------------ Philox
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// products; key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &b, int j) {
+    return j == 0 ? b.x : (j == 1 ? b.y : (j == 2 ? b.z : b.w));
+}
+
+// ------------------------------------------------------------------ init
+
+// Infinite-temperature start: site i of chain c takes word 0 of the block at
+// counter (i, 0, c, 1).
+__global__ void init_kernel(ProbDev p, int chain_begin, int n_chains) {
+    const int64_t total = (int64_t)p.N * n_chains;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / n_chains);
+        const int c = chain_begin + (int)(t % n_chains);
+        const uint4 b = philox4x32_10((uint32_t)i, 0u, (uint32_t)c, 1u, p.seed_lo, p.seed_hi);
+        uint8_t s;
+        if (p.model == kIsing)
+            s = (uint8_t)(b.x >> 31);
+        else
+            s = (uint8_t)(((uint64_t)b.x * (uint64_t)p.q) >> 32);
+        p.spins[(int64_t)i * p.C + c] = s;
+    }
+}
+
+// k (unsatisfied bonds, right and down bond of every site) and M of every chain.
+__global__ void energy_kernel(ProbDev p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.C) return;
+    const int L = p.L;
+    int k = 0, m = 0;
+    for (int y = 0; y < L; ++y) {
+        const int yd = (y + 1 == L) ? 0 : y + 1;
+        for (int x = 0; x < L; ++x) {
+            const int xr = (x + 1 == L) ? 0 : x + 1;
+            const uint8_t s = p.spins[(int64_t)(y * L + x) * p.C + c];
+            k += (s != p.spins[(int64_t)(y * L + xr) * p.C + c]);
+            k += (s != p.spins[(int64_t)(yd * L + x) * p.C + c]);
+            m += s ? 1 : -1;
+        }
+    }
+    p.k[c] = k;
+    p.m[c] = (p.model == kIsing) ? m : 0;
+}
+
+// ------------------------------------------------------------------ sweep
+
+__host__ __device__ inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+// LDS carve-up of one work item; identical on host (sizing) and device.
+struct LdsPlan {
+    int off_tab, off_spin, off_ring, total;
+};
+__host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
+    LdsPlan l;
+    l.off_tab = 0;
+    const int tab = p.table_lds ? round_up(p.trows * p.tcols * 4, 16) : 0;
+    l.off_spin = l.off_tab + tab;
+    const int spn = p.spin_lds ? round_up(p.N * it.spin_stride, 16) : 0;
+    l.off_ring = l.off_spin + spn;
+    const int words = (p.model == kIsing) ? 1 : 2;
+    const int ring = n_producer_waves > 0 ? 2 * kChunkSites * it.spin_stride * 4 * words : 0;
+    l.total = l.off_ring + ring;
+    return l;
+}
+
+int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
+    return lds_plan(p, it, n_producer_waves).total;
+}
+
+template <bool LDS>
+struct SpinRef {
+    uint8_t *base;    // LDS: site stride `stride`; HBM: site stride C
+    int stride;
+    __device__ __forceinline__ uint8_t ld(int site) const { return base[(int64_t)site * stride]; }
+    __device__ __forceinline__ void st(int site, uint8_t v) const { base[(int64_t)site * stride] = v; }
+};
+
+// Producer waves: stage the random words of chunk `t` (global chunk counter)
+// for every chain of the work item into LDS buffer t & 1.  Ising keeps the
+// acceptance word; Potts keeps the proposal offset floor(r (q-1) / 2^32) and
+// the acceptance word.
+template <int MODEL>
+__device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint32_t *ring_u, uint32_t *ring_r,
+                              int t, int nchunks, uint32_t sweep0, int ptid, int nprod_threads) {
+    const int sw = t / nchunks;
+    const int chunk = t - sw * nchunks;
+    const uint32_t sweep = sweep0 + (uint32_t)sw;
+    const int i0 = chunk * kChunkSites;
+    const int i1 = min(p.N, i0 + kChunkSites);
+    constexpr int SPB = (MODEL == kIsing) ? 4 : 2;   // sites per Philox block
+    const int nblk = (i1 - i0 + SPB - 1) / SPB;
+    const int total = nblk * it.nchains;
+    const int buf = t & 1;
+    const int ls = it.spin_stride;
+    uint32_t *ru = ring_u + buf * kChunkSites * ls;
+    uint32_t *rr = ring_r + buf * kChunkSites * ls;
+    for (int w = ptid; w < total; w += nprod_threads) {
+        const int b = w / it.nchains;
+        const int lane = w - b * it.nchains;
+        const int site0 = i0 + b * SPB;
+        const uint4 blk = philox4x32_10((uint32_t)(site0 / SPB), sweep, (uint32_t)(it.chain0 + lane), 0u,
+                                        p.seed_lo, p.seed_hi);
+        if (MODEL == kIsing) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (site0 + j < i1) ru[(site0 + j - i0) * ls + lane] = word_of(blk, j);
+        } else {
+            const uint32_t qm1 = (uint32_t)(p.q - 1);
+            rr[(site0 - i0) * ls + lane] = (uint32_t)(((uint64_t)blk.x * qm1) >> 32);
+            ru[(site0 - i0) * ls + lane] = blk.y;
+            if (site0 + 1 < i1) {
+                rr[(site0 + 1 - i0) * ls + lane] = (uint32_t)(((uint64_t)blk.z * qm1) >> 32);
+                ru[(site0 + 1 - i0) * ls + lane] = blk.w;
+            }
+        }
+    }
+}
+
+// Walker state of one lane (one chain).
+struct WalkState {
+    int row;        // table row: k/2 (Ising) or k (Potts)
+    int m;          // Ising magnetisation
+    int x, y, i;    // current site
+    uint4 blk;      // Philox block of the current site group (own-RNG mode)
+};
+
+template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
+__device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN_LDS> &S,
+                                            const uint32_t *tab, WalkState &st, uint32_t u, uint32_t tq) {
+    const int L = p.L, N = p.N, i = st.i, x = st.x, y = st.y;
+    const int il = (x == 0) ? i + L - 1 : i - 1;
+    const int ir = (x == L - 1) ? i - L + 1 : i + 1;
+    const int iu = (y == 0) ? i + N - L : i - L;
+    const int id = (y == L - 1) ? i - N + L : i + L;
+    const uint8_t s = S.ld(i);
+    const uint8_t a = S.ld(il), b = S.ld(ir), c = S.ld(iu), d = S.ld(id);
+    uint8_t snew;
+    int col, drow;
+    if (MODEL == kIsing) {
+        snew = s ^ 1u;
+        const int nd = (a != s) + (b != s) + (c != s) + (d != s);
+        // dk = 4 - 2 nd bonds; table row moves by dk/2 = 2 - nd, column 4 - nd
+        col = 4 - nd;
+        drow = 2 - nd;
+    } else {
+        const uint32_t q = (uint32_t)p.q;
+        uint32_t v = (uint32_t)s + 1u + tq;
+        snew = (uint8_t)(v >= q ? v - q : v);
+        const int before = (a != s) + (b != s) + (c != s) + (d != s);
+        const int after = (a != snew) + (b != snew) + (c != snew) + (d != snew);
+        drow = after - before;
+        col = drow + 4;
+    }
+    const uint32_t t = tab[st.row * (MODEL == kIsing ? 5 : 9) + col];
+    const bool acc = min(u, 0xFFFFFFFEu) < t;
+    if (acc) {
+        S.st(i, snew);
+        st.row += drow;
+        if (MODEL == kIsing) st.m += snew ? 2 : -2;
+    }
+    // advance to the next site
+    st.i = i + 1;
+    st.x = x + 1;
+    if (st.x == L) {
+        st.x = 0;
+        st.y = y + 1;
+    }
+}
+
+// The walker's pass over chunk t.
+template <int MODEL, bool SPIN_LDS, bool TAB_LDS, bool OWN_RNG>
+__device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it, const SpinRef<SPIN_LDS> &S,
+                                           const uint32_t *tab, const uint32_t *ring_u, const uint32_t *ring_r,
+                                           WalkState &st, int t, int nchunks, uint32_t sweep0, int lane,
+                                           int record) {
+    const int sw = t / nchunks;
+    const int chunk = t - sw * nchunks;
+    const uint32_t sweep = sweep0 + (uint32_t)sw;
+    const int i0 = chunk * kChunkSites;
+    const int i1 = min(p.N, i0 + kChunkSites);
+    if (chunk == 0) {
+        st.i = 0;
+        st.x = 0;
+        st.y = 0;
+    }
+    const uint32_t chain = (uint32_t)(it.chain0 + lane);
+    if (OWN_RNG) {
+        if (MODEL == kIsing) {
+            // N is a multiple of 4 for even L: whole blocks of four sites
+            for (int i = i0; i < i1; i += 4) {
+                const uint4 b = philox4x32_10((uint32_t)(i >> 2), sweep, chain, 0u, p.seed_lo, p.seed_hi);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.x, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.y, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.z, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.w, 0u);
+            }
+        } else {
+            const uint32_t qm1 = (uint32_t)(p.q - 1);
+            for (int i = i0; i < i1; i += 2) {
+                const uint4 b = philox4x32_10((uint32_t)(i >> 1), sweep, chain, 0u, p.seed_lo, p.seed_hi);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.y, (uint32_t)(((uint64_t)b.x * qm1) >> 32));
+                if (i + 1 < i1)
+                    update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.w,
+                                                          (uint32_t)(((uint64_t)b.z * qm1) >> 32));
+            }
+        }
+    } else {
+        const int ls = it.spin_stride;
+        const uint32_t *ru = ring_u + (t & 1) * kChunkSites * ls + lane;
+        const uint32_t *rr = ring_r + (t & 1) * kChunkSites * ls + lane;
+        for (int i = i0; i < i1; ++i) {
+            const uint32_t u = ru[(i - i0) * ls];
+            const uint32_t tq = (MODEL == kIsing) ? 0u : rr[(i - i0) * ls];
+            update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, u, tq);
+        }
+    }
+    if (i1 == p.N && record != kRecNone) {
+        const int k = (MODEL == kIsing) ? 2 * st.row : st.row;
+        const int c = it.chain0 + lane;
+        p.hist[(int64_t)k * p.C + c] += 1;
+        if (record == kRecProd) p.sabs[(int64_t)k * p.C + c] += (int64_t)(st.m < 0 ? -st.m : st.m);
+    }
+}
+
+template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
+__device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l, uint32_t sweep0) {
+    const LdsPlan plan = lds_plan(p, it, l.n_producer_waves);
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    // stage the table and the lattice
+    const uint32_t *tab = p.table;
+    if (TAB_LDS) {
+        uint32_t *t = reinterpret_cast<uint32_t *>(lds + plan.off_tab);
+        const int n = p.trows * p.tcols;
+        for (int j = tid; j < n; j += nthreads) t[j] = p.table[j];
+        tab = t;
+    }
+    SpinRef<SPIN_LDS> S;
+    if (SPIN_LDS) {
+        uint8_t *sp = reinterpret_cast<uint8_t *>(lds + plan.off_spin);
+        const int ls = it.spin_stride;
+        const int n = p.N * it.nchains;
+        for (int j = tid; j < n; j += nthreads) {
+            const int site = j / it.nchains, c = j - site * it.nchains;
+            sp[site * ls + c] = p.spins[(int64_t)site * p.C + it.chain0 + c];
+        }
+        S.base = sp + lane;
+        S.stride = ls;
+    } else {
+        S.base = p.spins + it.chain0 + lane;
+        S.stride = p.C;
+    }
+    uint32_t *ring_u = reinterpret_cast<uint32_t *>(lds + plan.off_ring);
+    uint32_t *ring_r = ring_u + 2 * kChunkSites * it.spin_stride;
+
+    const int nchunks = (p.N + kChunkSites - 1) / kChunkSites;
+    const int total_chunks = nchunks * l.n_sweeps;
+    const bool active = (wave == 0) && (lane < it.nchains);
+
+    WalkState st;
+    st.row = 0;
+    st.m = 0;
+    st.x = st.y = st.i = 0;
+    if (active) {
+        const int k = p.k[it.chain0 + lane];
+        st.row = (MODEL == kIsing) ? (k >> 1) : k;
+        st.m = p.m[it.chain0 + lane];
+    }
+
+    if (l.n_producer_waves == 0) {
+        __syncthreads();
+        if (active)
+            for (int t = 0; t < total_chunks; ++t)
+                walk_chunk<MODEL, SPIN_LDS, TAB_LDS, true>(p, it, S, tab, ring_u, ring_r, st, t, nchunks, sweep0,
+                                                           lane, l.record);
+    } else {
+        const int ptid = tid - 64;
+        const int nprod = nthreads - 64;
+        if (wave > 0) produce_chunk<MODEL>(p, it, ring_u, ring_r, 0, nchunks, sweep0, ptid, nprod);
+        __syncthreads();
+        for (int t = 0; t < total_chunks; ++t) {
+            if (wave == 0) {
+                if (active)
+                    walk_chunk<MODEL, SPIN_LDS, TAB_LDS, false>(p, it, S, tab, ring_u, ring_r, st, t, nchunks,
+                                                                sweep0, lane, l.record);
+            } else if (t + 1 < total_chunks) {
+                produce_chunk<MODEL>(p, it, ring_u, ring_r, t + 1, nchunks, sweep0, ptid, nprod);
+            }
+            __syncthreads();
+        }
+    }
+
+    if (active) {
+        p.k[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : st.row;
+        p.m[it.chain0 + lane] = st.m;
+    }
+    if (SPIN_LDS) {
+        __syncthreads();
+        const uint8_t *sp = reinterpret_cast<const uint8_t *>(lds + plan.off_spin);
+        const int ls = it.spin_stride;
+        const int n = p.N * it.nchains;
+        for (int j = tid; j < n; j += nthreads) {
+            const int site = j / it.nchains, c = j - site * it.nchains;
+            p.spins[(int64_t)site * p.C + it.chain0 + c] = sp[site * ls + c];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) sweep_kernel(SweepLaunch l) {
+    extern __shared__ __align__(16) char lds[];
+    const WorkItem it = l.items[blockIdx.x];
+    const ProbDev p = l.probs[it.prob];
+    const uint32_t sweep0 = *l.sweep_ctr;
+    if (p.model == kIsing) {
+        if (p.spin_lds) {
+            if (p.table_lds) run_item<kIsing, true, true>(p, it, lds, l, sweep0);
+            else run_item<kIsing, true, false>(p, it, lds, l, sweep0);
+        } else {
+            if (p.table_lds) run_item<kIsing, false, true>(p, it, lds, l, sweep0);
+            else run_item<kIsing, false, false>(p, it, lds, l, sweep0);
+        }
+    } else {
+        if (p.spin_lds) {
+            if (p.table_lds) run_item<kPotts, true, true>(p, it, lds, l, sweep0);
+            else run_item<kPotts, true, false>(p, it, lds, l, sweep0);
+        } else {
+            if (p.table_lds) run_item<kPotts, false, true>(p, it, lds, l, sweep0);
+            else run_item<kPotts, false, false>(p, it, lds, l, sweep0);
+        }
+    }
+}
+
+__global__ void advance_kernel(uint32_t *ctr, uint32_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += n;
+}
+
+// ------------------------------------------------------------------ merge
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// H[k] = sum_c hist[k][c] (Sec. 2: the chains' histograms are summed), and
+// the production |M| sums likewise; optionally clears what it read.
+__global__ void __launch_bounds__(256) merge_kernel(const ProbDev *probs, const MergeItem *items, int production,
+                                                     int clear) {
+    __shared__ int64_t red[2][4];
+    const MergeItem it = items[blockIdx.x];
+    const ProbDev p = probs[it.prob];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int b = it.bin0; b < it.bin0 + it.nb; ++b) {
+        int32_t *h = p.hist + (int64_t)b * p.C;
+        int64_t s = 0, sa = 0;
+        for (int c = tid; c < p.C; c += 256) {
+            s += h[c];
+            if (clear) h[c] = 0;
+        }
+        if (production && p.sabs) {
+            int64_t *a = p.sabs + (int64_t)b * p.C;
+            for (int c = tid; c < p.C; c += 256) {
+                sa += a[c];
+                if (clear) a[c] = 0;
+            }
+        }
+        s = wave_sum(s);
+        sa = wave_sum(sa);
+        if (lane == 0) {
+            red[0][wave] = s;
+            red[1][wave] = sa;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            p.H[b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+            if (production) p.S[b] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *dst, uint32_t v, size_t n) {
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x)
+        dst[j] = v;
+}
+
+__global__ void copy_bytes_kernel(uint8_t *dst, const uint8_t *src, size_t n) {
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x)
+        dst[j] = src[j];
+}
+
+// ------------------------------------------------------------------ reweighting
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Eq. (2) over energy bins, one workgroup per beta: a bin with n_k
+// measurements taken under weight W(E_k) contributes n_k exp(-beta E_k) / W(E_k).
+// Outputs <E>/N, beta^2 var(E)/N and <|M|>/N into out[0..2][j].
+__global__ void __launch_bounds__(256) reweight_kernel(const ProbDev *probs, int prob, const double *betas,
+                                                        int n_betas, double *out) {
+    __shared__ double red[4][4];
+    const ProbDev p = probs[prob];
+    const int j = blockIdx.x;
+    if (j >= n_betas) return;
+    const double beta = betas[j];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double N = (double)p.N;
+    const double estep = (p.model == kIsing) ? 2.0 : 1.0;
+    // pass 1: largest exponent
+    double amax = -INFINITY;
+    for (int b = tid; b < p.nbins; b += 256) {
+        const int64_t n = p.H[b];
+        if (n > 0) {
+            const double E = -2.0 * N + estep * b;
+            amax = fmax(amax, log((double)n) - p.lnW[b] - beta * E);
+        }
+    }
+    amax = wave_max_d(amax);
+    if (lane == 0) red[0][wave] = amax;
+    __syncthreads();
+    const double A = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+    __syncthreads();
+    // pass 2: Z, sum w E, sum of |M| weights
+    double z = 0, ze = 0, zm = 0;
+    for (int b = tid; b < p.nbins; b += 256) {
+        const int64_t n = p.H[b];
+        if (n > 0) {
+            const double E = -2.0 * N + estep * b;
+            const double e0 = -p.lnW[b] - beta * E - A;
+            const double w = exp(log((double)n) + e0);
+            z += w;
+            ze += w * E;
+            if (p.model == kIsing) zm += (double)p.S[b] * exp(e0);
+        }
+    }
+    z = wave_sum_d(z);
+    ze = wave_sum_d(ze);
+    zm = wave_sum_d(zm);
+    if (lane == 0) {
+        red[0][wave] = z;
+        red[1][wave] = ze;
+        red[2][wave] = zm;
+    }
+    __syncthreads();
+    const double Z = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double ZE = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double ZM = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    const double em = ZE / Z;
+    __syncthreads();
+    // pass 3: variance about the mean (two-pass)
+    double zv = 0;
+    for (int b = tid; b < p.nbins; b += 256) {
+        const int64_t n = p.H[b];
+        if (n > 0) {
+            const double E = -2.0 * N + estep * b;
+            const double w = exp(log((double)n) - p.lnW[b] - beta * E - A);
+            zv += w * (E - em) * (E - em);
+        }
+    }
+    zv = wave_sum_d(zv);
+    if (lane == 0) red[3][wave] = zv;
+    __syncthreads();
+    if (tid == 0) {
+        const double var = (red[3][0] + red[3][1] + red[3][2] + red[3][3]) / Z;
+        out[j] = em / N;
+        out[n_betas + j] = beta * beta * var / N;
+        out[2 * n_betas + j] = (p.model == kIsing) ? ZM / Z / N : __builtin_nan("");
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static int grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_init(const ProbDev &p, int chain_begin, int n_chains, hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(grid_for((int64_t)p.N * n_chains, 256)), dim3(256), 0, s, p, chain_begin,
+                       n_chains);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const ProbDev &p, hipStream_t s) {
+    hipLaunchKernelGGL(energy_kernel, dim3(grid_for(p.C, 64)), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t configure_sweep_kernel(int max_lds_bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+}
+
+hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s) {
+    const int threads = 64 * (1 + l.n_producer_waves);
+    hipLaunchKernelGGL(sweep_kernel, dim3(l.n_items), dim3(threads), l.lds_bytes, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(uint32_t *ctr, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, ctr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const ProbDev *probs, const MergeItem *items, int n_items, int production, int clear,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(merge_kernel, dim3(n_items), dim3(256), 0, s, probs, items, production, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for((int64_t)n, 256)), dim3(256), 0, s, dst, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bytes(void *dst, const void *src, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_bytes_kernel, dim3(grid_for((int64_t)n, 256)), dim3(256), 0, s, (uint8_t *)dst,
+                       (const uint8_t *)src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reweight(const ProbDev *probs, int prob, const double *betas, int n_betas, double *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(reweight_kernel, dim3(n_betas), dim3(256), 0, s, probs, prob, betas, n_betas, out);
+    return hipGetLastError();
+}
+
+}  // namespace muca

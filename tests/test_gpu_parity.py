@@ -1,0 +1,223 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Integer state (spins, energies, per-chain and merged histograms), the
+log-weights and the acceptance tables must match bit for bit; reweighted
+observables to a relative 1e-10.  Runs on an MI355X (marked gpu)."""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import gpu_available
+from workloads import C1, ISING, POTTS, Problem
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _pm():
+    import paper_1212_3975_amd as pm
+    return pm
+
+
+def _orc(prob: Problem, chain0=0, n=None):
+    return oracle.OracleRun(prob.model, prob.L, n if n is not None else prob.n_chains, prob.seed, q=prob.q,
+                            chain0=chain0)
+
+
+def _orc_iteration(orc, n_sweeps):
+    orc.hist[:] = 0
+    orc.sweeps(n_sweeps, oracle.REC_MUCA)
+    per_chain = orc.hist.copy()
+    H = orc.merged()
+    oracle.lib().orc_recursion(orc.n_bins, H, orc.lnW)
+    orc.T = oracle.build_table(orc.lnW)
+    orc.hist[:] = 0
+    return per_chain, H
+
+
+def _same_bits(a, b):
+    return np.array_equal(np.asarray(a, np.float64).view(np.uint64), np.asarray(b, np.float64).view(np.uint64))
+
+
+def _compare_iterations(ctx, orc, n_iters, n_sweeps, prob_idx=0, check_chain_hist=True):
+    for it in range(n_iters):
+        print(f"  iteration {it}", flush=True)
+        if check_chain_hist:
+            ctx.sweep(n_sweeps, 1)
+            ch = ctx.chain_hist(prob_idx)
+            stats = ctx.merge_update(True)[prob_idx]
+        else:
+            stats = ctx.iterate(n_sweeps)[prob_idx]
+        pc, H = _orc_iteration(orc, n_sweeps)
+        if check_chain_hist:
+            assert np.array_equal(ch, pc), f"per-chain histograms differ at iteration {it}"
+        assert np.array_equal(ctx.H(prob_idx), H), f"merged H differs at iteration {it}"
+        fl = oracle.flatness(H, orc.mask)
+        assert bool(stats["flat"]) == fl.flat and bool(stats["covered"]) == fl.covered
+        assert stats["total"] == orc.n_chains * n_sweeps
+        assert _same_bits(ctx.lnW(prob_idx), orc.lnW), f"lnW differs at iteration {it}"
+        assert np.array_equal(ctx.table(prob_idx), orc.T), f"T differs at iteration {it}"
+        assert np.array_equal(ctx.spins(prob_idx), orc.spins), f"spins differ at iteration {it}"
+        assert np.array_equal(ctx.k(prob_idx), orc.k), f"k differs at iteration {it}"
+        assert np.array_equal(ctx.m(prob_idx), orc.m), f"M differs at iteration {it}"
+
+
+def test_initial_state_matches():
+    pm = _pm()
+    for prob in (Problem(ISING, 8, 70, 5), Problem(POTTS, 5, 33, 6, q=8), Problem(ISING, 64, 64, 1)):
+        print("case", prob, flush=True)
+        with pm.Muca([prob]) as ctx:
+            orc = _orc(prob)
+            assert np.array_equal(ctx.spins(), orc.spins)
+            assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
+            assert np.array_equal(ctx.reachable(), orc.mask)
+            assert np.array_equal(ctx.table(), orc.T)
+
+
+def test_c1_ising_L8_full_run_bit_exact():
+    """Ising L = 8, 4 chains, 20 iterations of 1e4 sweeps: every iteration's
+    per-chain and merged histograms, weights, tables and spins."""
+    pm = _pm()
+    prob = C1.problems[0]
+    with pm.Muca([prob]) as ctx:
+        print("launch", ctx.launch_info(), flush=True)
+        orc = _orc(prob)
+        _compare_iterations(ctx, orc, C1.n_iters, C1.sweeps_per_iter)
+
+
+CONFIGS = [dict(rng_mode=1, chains_per_wg=16, spin_placement=1, table_placement=1),
+           dict(rng_mode=2, chains_per_wg=32, spin_placement=1, table_placement=2),
+           dict(rng_mode=3, chains_per_wg=64, spin_placement=2, table_placement=1),
+           dict(rng_mode=4, chains_per_wg=8, spin_placement=2, table_placement=2),
+           dict(rng_mode=2, chains_per_wg=4, spin_placement=1, table_placement=1)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "-".join(f"{k[:4]}{v}" for k, v in c.items()))
+@pytest.mark.parametrize("prob", [Problem(ISING, 6, 100, 7), Problem(POTTS, 3, 70, 8, q=8),
+                                  Problem(POTTS, 7, 41, 9, q=8), Problem(ISING, 12, 65, 10),
+                                  Problem(POTTS, 9, 20, 11, q=3)],
+                         ids=lambda p: f"{'ising' if p.model == 0 else 'potts'}L{p.L}C{p.n_chains}")
+def test_launch_configurations_bit_exact(prob, cfg):
+    """Ragged chain counts, lattices that end inside a chunk, every random-number
+    mode and placement: all give the oracle's trajectories."""
+    pm = _pm()
+    print("case", prob, cfg, flush=True)
+    with pm.Muca([prob], **cfg) as ctx:
+        orc = _orc(prob)
+        _compare_iterations(ctx, orc, 4, 150)
+
+
+def test_batched_problems_match_oracle_and_single_runs():
+    """Several problems in one launch: each equals its own oracle run and the
+    same problem run alone (batching invariance)."""
+    pm = _pm()
+    probs = [Problem(ISING, 16, 40, 1), Problem(ISING, 10, 64, 2), Problem(POTTS, 8, 50, 3, q=8),
+             Problem(POTTS, 5, 17, 4, q=8)]
+    with pm.Muca(probs) as ctx:
+        orcs = [_orc(p) for p in probs]
+        for it in range(3):
+            print(f"  iteration {it}", flush=True)
+            ctx.iterate(120)
+            for j, o in enumerate(orcs):
+                _, H = _orc_iteration(o, 120)
+                assert np.array_equal(ctx.H(j), H)
+                assert _same_bits(ctx.lnW(j), o.lnW)
+                assert np.array_equal(ctx.spins(j), o.spins)
+    with pm.Muca([probs[2]]) as alone:
+        for it in range(3):
+            alone.iterate(120)
+        assert np.array_equal(alone.spins(), orcs[2].spins)
+
+
+def test_graph_iteration_equals_eager():
+    pm = _pm()
+    prob = Problem(ISING, 16, 96, 12)
+    with pm.Muca([prob], use_graph=1) as g, pm.Muca([prob], use_graph=0) as e:
+        for it in range(4):
+            print(f"  iteration {it}", flush=True)
+            sg = g.iterate(300)[0]
+            se = e.iterate(300)[0]
+            assert sg == se
+            assert np.array_equal(g.H(), e.H())
+            assert _same_bits(g.lnW(), e.lnW())
+            assert np.array_equal(g.spins(), e.spins())
+        orc = _orc(prob)
+        for _ in range(4):
+            _orc_iteration(orc, 300)
+        assert np.array_equal(g.spins(), orc.spins) and _same_bits(g.lnW(), orc.lnW)
+
+
+def test_production_and_reweighting():
+    """Production counts and |M| sums bit for bit; Eq. (2) reweighting to
+    1e-10 relative on 200 inverse temperatures."""
+    pm = _pm()
+    for prob in (Problem(ISING, 8, 64, 21), Problem(POTTS, 6, 48, 22, q=8)):
+        print("case", prob, flush=True)
+        with pm.Muca([prob]) as ctx:
+            orc = _orc(prob)
+            for _ in range(8):
+                ctx.iterate(500)
+                _orc_iteration(orc, 500)
+            ctx.sweep(300, pm.REC_NONE)
+            ctx.clear_production()
+            ctx.sweep(2000, pm.REC_PROD)
+            cnt, sab = orc.production(300, 2000)
+            assert np.array_equal(ctx.prod_counts(), cnt)
+            if prob.model == ISING:
+                assert np.array_equal(ctx.prod_absm(), sab)
+            betas = np.linspace(0.3, 0.6, 200)
+            e, c, m = ctx.reweight(0, betas)
+            eo, co, mo = oracle.reweight(prob.model, prob.L, orc.lnW, cnt, sab, betas)
+            np.testing.assert_allclose(e, eo, rtol=1e-10, atol=0)
+            np.testing.assert_allclose(c, co, rtol=1e-10, atol=0)
+            if prob.model == ISING:
+                np.testing.assert_allclose(m, mo, rtol=1e-10, atol=0)
+            else:
+                assert np.all(np.isnan(m))
+
+
+def test_checkpoint_restore_continues_bit_exact():
+    pm = _pm()
+    prob = Problem(POTTS, 8, 40, 31, q=8)
+    with pm.Muca([prob]) as a:
+        for _ in range(3):
+            a.iterate(200)
+        blob = a.checkpoint()
+        for _ in range(2):
+            a.iterate(200)
+        with pm.Muca([prob]) as b:
+            b.restore(blob)
+            assert b.sweep_count() == 600
+            for _ in range(2):
+                b.iterate(200)
+            assert np.array_equal(a.spins(), b.spins()) and _same_bits(a.lnW(), b.lnW())
+            assert np.array_equal(a.H(), b.H())
+
+
+def test_set_log_weights_canonical_limit():
+    """Weights lnW = -beta E installed through the ABI give canonical
+    Metropolis; trajectories equal the oracle's with the same weights."""
+    pm = _pm()
+    prob = Problem(ISING, 10, 64, 41)
+    lnW = -0.44 * oracle.energies(ISING, 10)
+    with pm.Muca([prob]) as ctx:
+        ctx.set_log_weights(0, lnW)
+        orc = _orc(prob)
+        orc.set_log_weights(lnW)
+        assert np.array_equal(ctx.table(), orc.T)
+        ctx.sweep(500, pm.REC_MUCA)
+        orc.sweeps(500, oracle.REC_MUCA)
+        assert np.array_equal(ctx.chain_hist(), orc.hist)
+        assert np.array_equal(ctx.spins(), orc.spins)
+
+
+def test_errors_are_reported():
+    pm = _pm()
+    with pm.Muca([Problem(ISING, 8, 4, 1)], production=0) as ctx:
+        with pytest.raises(pm.MucaError):
+            ctx.sweep(10, pm.REC_PROD)
+        with pytest.raises(pm.MucaError):
+            ctx.set_log_weights(0, np.zeros(5))
+        with pytest.raises(pm.MucaError):
+            ctx.reweight(0, [0.4])
+        with pytest.raises(pm.MucaError):
+            ctx.set_log_weights(0, np.full(129, np.nan))
