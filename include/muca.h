@@ -112,7 +112,9 @@ typedef struct {
 /* Selected launch configuration of one problem (after tuning). */
 typedef struct {
     int32_t chains_per_wg, rng_mode, spin_placement, table_placement;
-    int32_t lds_bytes, n_workgroups, pad0, pad1;
+    int32_t lds_bytes, n_workgroups;
+    int32_t fast_walker;   /* 1: the four-sites-per-step Ising walker runs this problem */
+    int32_t pad1;
 } muca_launch_info;
 
 /* Bytes of device workspace that mucaInit needs for these problems. */

@@ -54,7 +54,7 @@ class LaunchInfo(ctypes.Structure):
     _fields_ = [("chains_per_wg", ctypes.c_int32), ("rng_mode", ctypes.c_int32),
                 ("spin_placement", ctypes.c_int32), ("table_placement", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+                ("fast_walker", ctypes.c_int32), ("pad1", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("pad")}

@@ -887,6 +887,7 @@ muca_status mucaLaunchInfo(muca_ctx ctx, int32_t prob, muca_launch_info *info) {
     int n = 0;
     for (auto &it : ctx->items) n += (it.prob == prob);
     info->n_workgroups = n;
+    info->fast_walker = uses_fast_walker(ctx->h_probdev[prob], ctx->n_producer_waves) ? 1 : 0;
     return MUCA_OK;
 }
 

@@ -64,6 +64,8 @@ struct SweepLaunch {
 
 // LDS bytes one work item needs (table, lattice, random-word ring).
 int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves);
+// Whether the sweep kernel takes the fast Ising walker for this problem.
+bool uses_fast_walker(const ProbDev &p, int n_producer_waves);
 // Raises the dynamic-LDS limit of the sweep kernel.
 hipError_t configure_sweep_kernel(int max_lds_bytes);
 

@@ -36,10 +36,6 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
-__device__ __forceinline__ uint32_t word_of(const uint4 &b, int j) {
-    return j == 0 ? b.x : (j == 1 ? b.y : (j == 2 ? b.z : b.w));
-}
-
 // ------------------------------------------------------------------ init
 
 // Infinite-temperature start: site i of chain c takes word 0 of the block at
@@ -85,6 +81,12 @@ __global__ void energy_kernel(ProbDev p) {
 __host__ __device__ inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 // LDS carve-up of one work item; identical on host (sizing) and device.
+//   table  trows x tcols words
+//   spins  ceil(N/4) x spin_stride words: word d of lane c holds sites
+//          4d..4d+3 of that chain, one byte each
+//   ring   two buffers of random words for kChunkSites sites: Ising one
+//          uint4 (four acceptance words) per 4 sites and lane, Potts one uint4
+//          (offset, word, offset, word) per 2 sites and lane
 struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
 };
@@ -93,7 +95,7 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
     l.off_tab = 0;
     const int tab = p.table_lds ? round_up(p.trows * p.tcols * 4, 16) : 0;
     l.off_spin = l.off_tab + tab;
-    const int spn = p.spin_lds ? round_up(p.N * it.spin_stride, 16) : 0;
+    const int spn = p.spin_lds ? round_up((p.N + 3) / 4 * it.spin_stride * 4, 16) : 0;
     l.off_ring = l.off_spin + spn;
     const int words = (p.model == kIsing) ? 1 : 2;
     const int ring = n_producer_waves > 0 ? 2 * kChunkSites * it.spin_stride * 4 * words : 0;
@@ -105,21 +107,35 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     return lds_plan(p, it, n_producer_waves).total;
 }
 
+// The fast Ising walker needs whole 64-site chunks, at least four dwords per
+// row, both arrays in LDS and producer waves.
+__host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves) {
+    return p.model == kIsing && p.L % 8 == 0 && p.L >= 16 && p.spin_lds && p.table_lds && n_producer_waves > 0;
+}
+
+bool uses_fast_walker(const ProbDev &p, int n_producer_waves) { return fast_ising_ok(p, n_producer_waves); }
+
 template <bool LDS>
 struct SpinRef {
-    uint8_t *base;    // LDS: site stride `stride`; HBM: site stride C
+    // LDS: base = lattice + 4 * lane, stride = bytes per dword row (4 * spin_stride)
+    // HBM: base = spins + chain, stride = C
+    uint8_t *base;
     int stride;
-    __device__ __forceinline__ uint8_t ld(int site) const { return base[(int64_t)site * stride]; }
-    __device__ __forceinline__ void st(int site, uint8_t v) const { base[(int64_t)site * stride] = v; }
+    __device__ __forceinline__ int64_t off(int site) const {
+        return LDS ? (int64_t)(site >> 2) * stride + (site & 3) : (int64_t)site * stride;
+    }
+    __device__ __forceinline__ uint8_t ld(int site) const { return base[off(site)]; }
+    __device__ __forceinline__ void st(int site, uint8_t v) const { base[off(site)] = v; }
 };
 
 // Producer waves: stage the random words of chunk `t` (global chunk counter)
-// for every chain of the work item into LDS buffer t & 1.  Ising keeps the
-// acceptance word; Potts keeps the proposal offset floor(r (q-1) / 2^32) and
-// the acceptance word.
+// for every chain of the work item into LDS buffer t & 1.  Acceptance words
+// are stored as min(u, 0xfffffffe), so that the walker's single comparison
+// "stored < T" means T == 0xffffffff or u < T.  Potts also stores the
+// proposal offset floor(r (q-1) / 2^32).
 template <int MODEL>
-__device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint32_t *ring_u, uint32_t *ring_r,
-                              int t, int nchunks, uint32_t sweep0, int ptid, int nprod_threads) {
+__device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring, int t, int nchunks,
+                              uint32_t sweep0, int ptid, int nprod_threads) {
     const int sw = t / nchunks;
     const int chunk = t - sw * nchunks;
     const uint32_t sweep = sweep0 + (uint32_t)sw;
@@ -128,38 +144,31 @@ __device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint32_t *ri
     constexpr int SPB = (MODEL == kIsing) ? 4 : 2;   // sites per Philox block
     const int nblk = (i1 - i0 + SPB - 1) / SPB;
     const int total = nblk * it.nchains;
-    const int buf = t & 1;
     const int ls = it.spin_stride;
-    uint32_t *ru = ring_u + buf * kChunkSites * ls;
-    uint32_t *rr = ring_r + buf * kChunkSites * ls;
+    uint4 *r = ring + (t & 1) * (kChunkSites / SPB) * ls;
+    const uint32_t qm1 = (uint32_t)(p.q - 1);
     for (int w = ptid; w < total; w += nprod_threads) {
         const int b = w / it.nchains;
         const int lane = w - b * it.nchains;
-        const int site0 = i0 + b * SPB;
-        const uint4 blk = philox4x32_10((uint32_t)(site0 / SPB), sweep, (uint32_t)(it.chain0 + lane), 0u,
+        const uint4 blk = philox4x32_10((uint32_t)(i0 / SPB + b), sweep, (uint32_t)(it.chain0 + lane), 0u,
                                         p.seed_lo, p.seed_hi);
+        uint4 o;
         if (MODEL == kIsing) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (site0 + j < i1) ru[(site0 + j - i0) * ls + lane] = word_of(blk, j);
+            o = make_uint4(min(blk.x, 0xFFFFFFFEu), min(blk.y, 0xFFFFFFFEu), min(blk.z, 0xFFFFFFFEu),
+                           min(blk.w, 0xFFFFFFFEu));
         } else {
-            const uint32_t qm1 = (uint32_t)(p.q - 1);
-            rr[(site0 - i0) * ls + lane] = (uint32_t)(((uint64_t)blk.x * qm1) >> 32);
-            ru[(site0 - i0) * ls + lane] = blk.y;
-            if (site0 + 1 < i1) {
-                rr[(site0 + 1 - i0) * ls + lane] = (uint32_t)(((uint64_t)blk.z * qm1) >> 32);
-                ru[(site0 + 1 - i0) * ls + lane] = blk.w;
-            }
+            o = make_uint4((uint32_t)(((uint64_t)blk.x * qm1) >> 32), min(blk.y, 0xFFFFFFFEu),
+                           (uint32_t)(((uint64_t)blk.z * qm1) >> 32), min(blk.w, 0xFFFFFFFEu));
         }
+        r[b * ls + lane] = o;
     }
 }
 
-// Walker state of one lane (one chain).
+// Walker state of one lane (one chain) in the generic walker.
 struct WalkState {
     int row;        // table row: k/2 (Ising) or k (Potts)
     int m;          // Ising magnetisation
     int x, y, i;    // current site
-    uint4 blk;      // Philox block of the current site group (own-RNG mode)
 };
 
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
@@ -190,13 +199,12 @@ __device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN
         col = drow + 4;
     }
     const uint32_t t = tab[st.row * (MODEL == kIsing ? 5 : 9) + col];
-    const bool acc = min(u, 0xFFFFFFFEu) < t;
+    const bool acc = u < t;   // u arrives as min(u, 0xfffffffe)
     if (acc) {
         S.st(i, snew);
         st.row += drow;
         if (MODEL == kIsing) st.m += snew ? 2 : -2;
     }
-    // advance to the next site
     st.i = i + 1;
     st.x = x + 1;
     if (st.x == L) {
@@ -205,12 +213,13 @@ __device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN
     }
 }
 
-// The walker's pass over chunk t.
+__device__ __forceinline__ uint32_t clampw(uint32_t u) { return min(u, 0xFFFFFFFEu); }
+
+// The generic walker's pass over chunk t.
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS, bool OWN_RNG>
 __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it, const SpinRef<SPIN_LDS> &S,
-                                           const uint32_t *tab, const uint32_t *ring_u, const uint32_t *ring_r,
-                                           WalkState &st, int t, int nchunks, uint32_t sweep0, int lane,
-                                           int record) {
+                                           const uint32_t *tab, const uint4 *ring, WalkState &st, int t,
+                                           int nchunks, uint32_t sweep0, int lane, int record) {
     const int sw = t / nchunks;
     const int chunk = t - sw * nchunks;
     const uint32_t sweep = sweep0 + (uint32_t)sw;
@@ -227,29 +236,40 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
             // N is a multiple of 4 for even L: whole blocks of four sites
             for (int i = i0; i < i1; i += 4) {
                 const uint4 b = philox4x32_10((uint32_t)(i >> 2), sweep, chain, 0u, p.seed_lo, p.seed_hi);
-                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.x, 0u);
-                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.y, 0u);
-                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.z, 0u);
-                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.w, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, clampw(b.x), 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, clampw(b.y), 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, clampw(b.z), 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, clampw(b.w), 0u);
             }
         } else {
             const uint32_t qm1 = (uint32_t)(p.q - 1);
             for (int i = i0; i < i1; i += 2) {
                 const uint4 b = philox4x32_10((uint32_t)(i >> 1), sweep, chain, 0u, p.seed_lo, p.seed_hi);
-                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.y, (uint32_t)(((uint64_t)b.x * qm1) >> 32));
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, clampw(b.y),
+                                                      (uint32_t)(((uint64_t)b.x * qm1) >> 32));
                 if (i + 1 < i1)
-                    update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, b.w,
+                    update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, clampw(b.w),
                                                           (uint32_t)(((uint64_t)b.z * qm1) >> 32));
             }
         }
     } else {
         const int ls = it.spin_stride;
-        const uint32_t *ru = ring_u + (t & 1) * kChunkSites * ls + lane;
-        const uint32_t *rr = ring_r + (t & 1) * kChunkSites * ls + lane;
-        for (int i = i0; i < i1; ++i) {
-            const uint32_t u = ru[(i - i0) * ls];
-            const uint32_t tq = (MODEL == kIsing) ? 0u : rr[(i - i0) * ls];
-            update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, u, tq);
+        if (MODEL == kIsing) {
+            const uint4 *r = ring + (t & 1) * (kChunkSites / 4) * ls + lane;
+            for (int i = i0; i < i1; i += 4) {
+                const uint4 w = r[((i - i0) >> 2) * ls];
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.x, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.y, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.z, 0u);
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.w, 0u);
+            }
+        } else {
+            const uint4 *r = ring + (t & 1) * (kChunkSites / 2) * ls + lane;
+            for (int i = i0; i < i1; i += 2) {
+                const uint4 w = r[((i - i0) >> 1) * ls];
+                update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.y, w.x);
+                if (i + 1 < i1) update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.w, w.z);
+            }
         }
     }
     if (i1 == p.N && record != kRecNone) {
@@ -259,6 +279,160 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
         if (record == kRecProd) p.sabs[(int64_t)k * p.C + c] += (int64_t)(st.m < 0 ? -st.m : st.m);
     }
 }
+
+// ------------------------------------------------------------------ fast Ising walker
+//
+// Sites are handled four at a time: one dword holds four consecutive sites
+// of a row (one byte each, 0/1).  With byte-wise xor and add, one dword op
+// yields for all four sites the number of disagreeing neighbours among up,
+// down and right; the left neighbour is the only one that an earlier update
+// of the same sweep can still change, so each site gets two candidate
+// counts, D0 (left neighbour kept) and D1 (left neighbour flipped), chosen
+// by the previous site's acceptance.  A move with D disagreeing neighbours
+// changes k by 2(2 - D), i.e. the table row by 2 - D, and reads column 4 - D.
+//
+// The dependence from one site to the next is then only "select, compare":
+// while site j is decided, the table words of site j+1 for both outcomes of
+// site j are already being read (row unchanged with D0, or row moved with
+// D1).  Rows are addressed by their LDS byte offset, 20 bytes per row.
+
+__device__ __forceinline__ uint32_t lds_word(const char *lds, uint32_t byte_off) {
+    return *reinterpret_cast<const uint32_t *>(lds + byte_off);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t v, int j) { return (v >> (8 * j)) & 0xFFu; }
+
+struct FastBulk {
+    uint32_t cur;   // old spins of the dword
+    uint32_t d0;    // bytes: disagreeing neighbours if the left neighbour keeps its old value
+    uint32_t d1;    // bytes: ... if the left neighbour has flipped
+};
+
+__device__ __forceinline__ FastBulk fast_bulk(const uint32_t *sp, int ls, int d, int W, int NW) {
+    const int w = d % W;
+    const int drow = d - w;                       // first dword of the row
+    const uint32_t cur = sp[d * ls];
+    const uint32_t prv = sp[(w == 0 ? drow + W - 1 : d - 1) * ls];
+    const uint32_t nxt = sp[(w == W - 1 ? drow : d + 1) * ls];
+    const uint32_t up = sp[(d >= W ? d - W : d + NW - W) * ls];
+    const uint32_t dn = sp[(d + W < NW ? d + W : d + W - NW) * ls];
+    // right neighbours: bytes cur1 cur2 cur3 nxt0; left (old): prv3 cur0 cur1 cur2
+    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
+    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);
+    const uint32_t s3 = (cur ^ up) + (cur ^ dn) + (cur ^ rn);
+    const uint32_t ml = cur ^ lo;
+    FastBulk b;
+    b.cur = cur;
+    b.d0 = s3 + ml;
+    b.d1 = s3 + (ml ^ 0x01010101u);
+    // the first site of a row has its left neighbour at the row's end, which
+    // this sweep has not visited yet: both candidates agree
+    if (w == 0) b.d1 = (b.d1 & 0xFFFFFF00u) | (b.d0 & 0xFFu);
+    return b;
+}
+
+__device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                               uint32_t sweep0, const LdsPlan &plan) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int L = p.L, W = L >> 2, NW = p.N >> 2;
+    const int ls = it.spin_stride;
+    const int nthreads = blockDim.x;
+    const int nchunks = p.N / kChunkSites;
+    const int total_chunks = nchunks * l.n_sweeps;
+    const bool active = (wave == 0) && (lane < it.nchains);
+    uint32_t *sp = reinterpret_cast<uint32_t *>(lds + plan.off_spin) + lane;
+    uint4 *ring = reinterpret_cast<uint4 *>(lds + plan.off_ring);
+    const uint4 *wring = ring + lane;
+    const uint32_t tab0 = (uint32_t)plan.off_tab;
+
+    // walker registers
+    uint32_t R = 0, C = 0, tA = 0, tB = 0;   // row offsets before / after the last site's move
+    bool acc = false;
+    int m = 0;
+    FastBulk nb{0, 0, 0};
+    if (active) {
+        const int k = p.k[it.chain0 + lane];
+        m = p.m[it.chain0 + lane];
+        R = tab0 + 20u * (uint32_t)(k >> 1);
+        C = R;
+        nb = fast_bulk(sp, ls, 0, W, NW);
+        // candidates of site 0: left neighbour never flipped yet
+        tA = lds_word(lds, R + 16u - 4u * byte_of(nb.d0, 0));
+        tB = tA;
+    }
+
+    const int ptid = tid - 64, nprod = nthreads - 64;
+    if (wave > 0) produce_chunk<kIsing>(p, it, ring, 0, nchunks, sweep0, ptid, nprod);
+    __syncthreads();
+    int d = 0;   // dword within the sweep
+    for (int t = 0; t < total_chunks; ++t) {
+        if (wave == 0) {
+            if (active) {
+                const uint4 *wr = wring + (t & 1) * (kChunkSites / 4) * ls;
+#pragma unroll 1
+                for (int q4 = 0; q4 < kChunkSites / 4; ++q4) {
+                    const FastBulk b = nb;
+                    const int dn = (d + 1 == NW) ? 0 : d + 1;
+                    nb = fast_bulk(sp, ls, dn, W, NW);
+                    const uint4 u = wr[q4 * ls];
+                    uint32_t fb = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        // row before this site's move, and this site's candidate count
+                        const uint32_t Rj = acc ? C : R;
+                        const uint32_t Dj = acc ? byte_of(b.d1, j) : byte_of(b.d0, j);
+                        const uint32_t Cj = Rj + 40u - 20u * Dj;
+                        // table words of the next site for both outcomes of this one
+                        const uint32_t a0 = (j < 3) ? byte_of(b.d0, j + 1) : byte_of(nb.d0, 0);
+                        const uint32_t a1 = (j < 3) ? byte_of(b.d1, j + 1) : byte_of(nb.d1, 0);
+                        const uint32_t nA = lds_word(lds, Rj + 16u - 4u * a0);
+                        const uint32_t nB = lds_word(lds, Cj + 16u - 4u * a1);
+                        const uint32_t tj = acc ? tB : tA;
+                        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+                        acc = uj < tj;
+                        fb |= (uint32_t)acc << j;
+                        R = Rj;
+                        C = Cj;
+                        tA = nA;
+                        tB = nB;
+                    }
+                    const uint32_t flips = (fb * 0x204081u) & 0x01010101u;
+                    if (l.record == kRecProd) {
+                        // each flip of a 0 adds 2 to M, each flip of a 1 subtracts 2
+                        const int nflip = __builtin_popcount(fb);
+                        const int nflip1 = __builtin_popcount(flips & b.cur);
+                        m += 2 * (nflip - 2 * nflip1);
+                    }
+                    sp[d * ls] = b.cur ^ flips;
+                    d = dn;
+                    if (d == 0 && l.record != kRecNone) {
+                        const uint32_t Rk = acc ? C : R;
+                        const int k = 2 * (int)((Rk - tab0) / 20u);
+                        const int c = it.chain0 + lane;
+                        p.hist[(int64_t)k * p.C + c] += 1;
+                        if (l.record == kRecProd) p.sabs[(int64_t)k * p.C + c] += (int64_t)(m < 0 ? -m : m);
+                    }
+                }
+            }
+        } else if (t + 1 < total_chunks) {
+            produce_chunk<kIsing>(p, it, ring, t + 1, nchunks, sweep0, ptid, nprod);
+        }
+        __syncthreads();
+    }
+
+    if (active) {
+        const uint32_t Rk = acc ? C : R;
+        p.k[it.chain0 + lane] = 2 * (int)((Rk - tab0) / 20u);
+        // magnetisation from the lattice (tracked only while producing)
+        int ones = 0;
+        for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(sp[dd * ls]);
+        p.m[it.chain0 + lane] = 2 * ones - p.N;
+    }
+}
+
+// ------------------------------------------------------------------ work item driver
 
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
 __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l, uint32_t sweep0) {
@@ -277,72 +451,72 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
         tab = t;
     }
     SpinRef<SPIN_LDS> S;
+    const int ls = it.spin_stride;
     if (SPIN_LDS) {
         uint8_t *sp = reinterpret_cast<uint8_t *>(lds + plan.off_spin);
-        const int ls = it.spin_stride;
         const int n = p.N * it.nchains;
         for (int j = tid; j < n; j += nthreads) {
             const int site = j / it.nchains, c = j - site * it.nchains;
-            sp[site * ls + c] = p.spins[(int64_t)site * p.C + it.chain0 + c];
+            sp[((site >> 2) * ls + c) * 4 + (site & 3)] = p.spins[(int64_t)site * p.C + it.chain0 + c];
         }
-        S.base = sp + lane;
-        S.stride = ls;
+        S.base = sp + 4 * lane;
+        S.stride = 4 * ls;
     } else {
         S.base = p.spins + it.chain0 + lane;
         S.stride = p.C;
     }
-    uint32_t *ring_u = reinterpret_cast<uint32_t *>(lds + plan.off_ring);
-    uint32_t *ring_r = ring_u + 2 * kChunkSites * it.spin_stride;
+    uint4 *ring = reinterpret_cast<uint4 *>(lds + plan.off_ring);
 
-    const int nchunks = (p.N + kChunkSites - 1) / kChunkSites;
-    const int total_chunks = nchunks * l.n_sweeps;
-    const bool active = (wave == 0) && (lane < it.nchains);
-
-    WalkState st;
-    st.row = 0;
-    st.m = 0;
-    st.x = st.y = st.i = 0;
-    if (active) {
-        const int k = p.k[it.chain0 + lane];
-        st.row = (MODEL == kIsing) ? (k >> 1) : k;
-        st.m = p.m[it.chain0 + lane];
-    }
-
-    if (l.n_producer_waves == 0) {
+    if (MODEL == kIsing && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
         __syncthreads();
-        if (active)
-            for (int t = 0; t < total_chunks; ++t)
-                walk_chunk<MODEL, SPIN_LDS, TAB_LDS, true>(p, it, S, tab, ring_u, ring_r, st, t, nchunks, sweep0,
-                                                           lane, l.record);
+        run_ising_fast(p, it, lds, l, sweep0, plan);
     } else {
-        const int ptid = tid - 64;
-        const int nprod = nthreads - 64;
-        if (wave > 0) produce_chunk<MODEL>(p, it, ring_u, ring_r, 0, nchunks, sweep0, ptid, nprod);
-        __syncthreads();
-        for (int t = 0; t < total_chunks; ++t) {
-            if (wave == 0) {
-                if (active)
-                    walk_chunk<MODEL, SPIN_LDS, TAB_LDS, false>(p, it, S, tab, ring_u, ring_r, st, t, nchunks,
-                                                                sweep0, lane, l.record);
-            } else if (t + 1 < total_chunks) {
-                produce_chunk<MODEL>(p, it, ring_u, ring_r, t + 1, nchunks, sweep0, ptid, nprod);
-            }
-            __syncthreads();
+        const int nchunks = (p.N + kChunkSites - 1) / kChunkSites;
+        const int total_chunks = nchunks * l.n_sweeps;
+        const bool active = (wave == 0) && (lane < it.nchains);
+        WalkState st;
+        st.row = 0;
+        st.m = 0;
+        st.x = st.y = st.i = 0;
+        if (active) {
+            const int k = p.k[it.chain0 + lane];
+            st.row = (MODEL == kIsing) ? (k >> 1) : k;
+            st.m = p.m[it.chain0 + lane];
         }
-    }
-
-    if (active) {
-        p.k[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : st.row;
-        p.m[it.chain0 + lane] = st.m;
+        if (l.n_producer_waves == 0) {
+            __syncthreads();
+            if (active)
+                for (int t = 0; t < total_chunks; ++t)
+                    walk_chunk<MODEL, SPIN_LDS, TAB_LDS, true>(p, it, S, tab, ring, st, t, nchunks, sweep0, lane,
+                                                               l.record);
+        } else {
+            const int ptid = tid - 64;
+            const int nprod = nthreads - 64;
+            if (wave > 0) produce_chunk<MODEL>(p, it, ring, 0, nchunks, sweep0, ptid, nprod);
+            __syncthreads();
+            for (int t = 0; t < total_chunks; ++t) {
+                if (wave == 0) {
+                    if (active)
+                        walk_chunk<MODEL, SPIN_LDS, TAB_LDS, false>(p, it, S, tab, ring, st, t, nchunks, sweep0,
+                                                                    lane, l.record);
+                } else if (t + 1 < total_chunks) {
+                    produce_chunk<MODEL>(p, it, ring, t + 1, nchunks, sweep0, ptid, nprod);
+                }
+                __syncthreads();
+            }
+        }
+        if (active) {
+            p.k[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : st.row;
+            p.m[it.chain0 + lane] = st.m;
+        }
     }
     if (SPIN_LDS) {
         __syncthreads();
         const uint8_t *sp = reinterpret_cast<const uint8_t *>(lds + plan.off_spin);
-        const int ls = it.spin_stride;
         const int n = p.N * it.nchains;
         for (int j = tid; j < n; j += nthreads) {
             const int site = j / it.nchains, c = j - site * it.nchains;
-            p.spins[(int64_t)site * p.C + it.chain0 + c] = sp[site * ls + c];
+            p.spins[(int64_t)site * p.C + it.chain0 + c] = sp[((site >> 2) * ls + c) * 4 + (site & 3)];
         }
     }
 }
