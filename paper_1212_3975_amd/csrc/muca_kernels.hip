@@ -90,11 +90,22 @@ __host__ __device__ inline int round_up(int v, int a) { return (v + a - 1) / a *
 struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
 };
+__host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves);
+__host__ __device__ constexpr int fast_rows_per_chunk(int L) { return (64 + L - 1) / L; }
+__host__ __device__ constexpr int fast_lane_stride(int L) { return ((L * L / 4) % 2) ? L * L / 4 : L * L / 4 + 1; }
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
     l.off_tab = 0;
     const int tab = p.table_lds ? round_up(p.trows * p.tcols * 4, 16) : 0;
     l.off_spin = l.off_tab + tab;
+    if (fast_ising_ok(p, n_producer_waves)) {
+        // lane-major lattice with an odd dword stride; ring [2][lane][chunk dwords + 1] uint4
+        const int W = p.L / 4;
+        const int cdw = fast_rows_per_chunk(p.L) * W;
+        l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
+        l.total = l.off_ring + 2 * it.nchains * (cdw + 1) * 16;
+        return l;
+    }
     const int spn = p.spin_lds ? round_up((p.N + 3) / 4 * it.spin_stride * 4, 16) : 0;
     l.off_ring = l.off_spin + spn;
     const int words = (p.model == kIsing) ? 1 : 2;
@@ -107,10 +118,11 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     return lds_plan(p, it, n_producer_waves).total;
 }
 
-// The fast Ising walker needs whole 64-site chunks, at least four dwords per
-// row, both arrays in LDS and producer waves.
+// The fast Ising walker has compiled shapes for these sizes and needs both
+// arrays in LDS and producer waves.
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves) {
-    return p.model == kIsing && p.L % 8 == 0 && p.L >= 16 && p.spin_lds && p.table_lds && n_producer_waves > 0;
+    const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32 || p.L == 48 || p.L == 64;
+    return p.model == kIsing && size_ok && p.spin_lds && p.table_lds && n_producer_waves > 0;
 }
 
 bool uses_fast_walker(const ProbDev &p, int n_producer_waves) { return fast_ising_ok(p, n_producer_waves); }
@@ -283,141 +295,216 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
 // ------------------------------------------------------------------ fast Ising walker
 //
 // Sites are handled four at a time: one dword holds four consecutive sites
-// of a row (one byte each, 0/1).  With byte-wise xor and add, one dword op
-// yields for all four sites the number of disagreeing neighbours among up,
-// down and right; the left neighbour is the only one that an earlier update
-// of the same sweep can still change, so each site gets two candidate
-// counts, D0 (left neighbour kept) and D1 (left neighbour flipped), chosen
-// by the previous site's acceptance.  A move with D disagreeing neighbours
-// changes k by 2(2 - D), i.e. the table row by 2 - D, and reads column 4 - D.
+// of a row (one byte each, 0/1).  With byte-wise xor and add, a few dword ops
+// give for all four sites the number of disagreeing neighbours among up,
+// down and right; the left neighbour is the only one an earlier update of
+// the same sweep can still change, so each site gets two candidate counts,
+// D0 (left neighbour kept) and D1 (left neighbour flipped), chosen by the
+// previous site's acceptance.  A move with D disagreeing neighbours changes
+// k by 2(2 - D): the table row moves by 2 - D rows (20 bytes each) and the
+// move reads column 4 - D (byte offset 16 - 4D).  Both byte maps are applied
+// to four sites at once with v_perm as a lookup table.
 //
 // The dependence from one site to the next is then only "select, compare":
 // while site j is decided, the table words of site j+1 for both outcomes of
-// site j are already being read (row unchanged with D0, or row moved with
-// D1).  Rows are addressed by their LDS byte offset, 20 bytes per row.
+// site j are already in flight (row unchanged with D0, or row moved with D1).
+//
+// Layout: each lane's lattice is contiguous in LDS (row-major dwords, an odd
+// dword stride between lanes so that lanes hit different banks); L is a
+// compile-time constant, so every neighbour read is a fixed offset from one
+// of three row pointers.  The random words of a chunk of rows sit in a ring
+// [buffer][lane][dword] of uint4.
 
-__device__ __forceinline__ uint32_t lds_word(const char *lds, uint32_t byte_off) {
-    return *reinterpret_cast<const uint32_t *>(lds + byte_off);
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u4;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) int64_t g_i64;
+
+__device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(const lds_u32 *)(size_t)a; }
+__device__ __forceinline__ void lds_st(uint32_t a, uint32_t v) { *(lds_u32 *)(size_t)a = v; }
+__device__ __forceinline__ uint4 lds_ld4(uint32_t a) {
+    const u32x4 v = *(const lds_u4 *)(size_t)a;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_st4(uint32_t a, uint4 v) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(lds_u4 *)(size_t)a = w;
 }
 
-__device__ __forceinline__ uint32_t byte_of(uint32_t v, int j) { return (v >> (8 * j)) & 0xFFu; }
+__device__ __forceinline__ uint32_t ubyte(uint32_t v, int j) { return (v >> (8 * j)) & 0xFFu; }
+__device__ __forceinline__ int32_t sbyte(uint32_t v, int j) { return (int32_t)(int8_t)(uint8_t)(v >> (8 * j)); }
 
 struct FastBulk {
-    uint32_t cur;   // old spins of the dword
-    uint32_t d0;    // bytes: disagreeing neighbours if the left neighbour keeps its old value
-    uint32_t d1;    // bytes: ... if the left neighbour has flipped
+    uint32_t cur;      // old spins of the dword
+    uint32_t a0, a1;   // bytes: column byte offset 16 - 4D for D0 / D1
+    uint32_t e0, e1;   // bytes (int8): row byte step 40 - 20D for D0 / D1
 };
 
-__device__ __forceinline__ FastBulk fast_bulk(const uint32_t *sp, int ls, int d, int W, int NW) {
-    const int w = d % W;
-    const int drow = d - w;                       // first dword of the row
-    const uint32_t cur = sp[d * ls];
-    const uint32_t prv = sp[(w == 0 ? drow + W - 1 : d - 1) * ls];
-    const uint32_t nxt = sp[(w == W - 1 ? drow : d + 1) * ls];
-    const uint32_t up = sp[(d >= W ? d - W : d + NW - W) * ls];
-    const uint32_t dn = sp[(d + W < NW ? d + W : d + W - NW) * ls];
+template <bool ROW_START>
+__device__ __forceinline__ FastBulk fast_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn) {
     // right neighbours: bytes cur1 cur2 cur3 nxt0; left (old): prv3 cur0 cur1 cur2
     const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
     const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);
     const uint32_t s3 = (cur ^ up) + (cur ^ dn) + (cur ^ rn);
     const uint32_t ml = cur ^ lo;
-    FastBulk b;
-    b.cur = cur;
-    b.d0 = s3 + ml;
-    b.d1 = s3 + (ml ^ 0x01010101u);
+    const uint32_t d0 = s3 + ml;
+    uint32_t d1 = s3 + (ml ^ 0x01010101u);
     // the first site of a row has its left neighbour at the row's end, which
     // this sweep has not visited yet: both candidates agree
-    if (w == 0) b.d1 = (b.d1 & 0xFFFFFF00u) | (b.d0 & 0xFFu);
+    if (ROW_START) d1 = (d1 & 0xFFFFFF00u) | (d0 & 0xFFu);
+    FastBulk b;
+    b.cur = cur;
+    b.a0 = __builtin_amdgcn_perm(0u, 0x04080C10u, d0);           // 16,12,8,4,0
+    b.a1 = __builtin_amdgcn_perm(0u, 0x04080C10u, d1);
+    b.e0 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d0);        // 40,20,0,-20,-40
+    b.e1 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d1);
     return b;
 }
 
+template <int L>
 __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int L = p.L, W = L >> 2, NW = p.N >> 2;
-    const int ls = it.spin_stride;
+    constexpr int W = L / 4;                  // dwords per row
+    constexpr int NW = L * L / 4;             // dwords per lattice
+    constexpr int RPC = fast_rows_per_chunk(L);
+    constexpr int CDW = RPC * W;              // dwords per chunk
+    constexpr int NCH = L / RPC;              // chunks per sweep
+    constexpr int P = fast_lane_stride(L);    // dwords between lanes
+    static_assert(L % RPC == 0 && W >= 4, "fast walker shape");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nthreads = blockDim.x;
-    const int nchunks = p.N / kChunkSites;
-    const int total_chunks = nchunks * l.n_sweeps;
-    const bool active = (wave == 0) && (lane < it.nchains);
-    uint32_t *sp = reinterpret_cast<uint32_t *>(lds + plan.off_spin) + lane;
-    uint4 *ring = reinterpret_cast<uint4 *>(lds + plan.off_ring);
-    const uint4 *wring = ring + lane;
-    const uint32_t tab0 = (uint32_t)plan.off_tab;
+    const int nch = it.nchains;
+    const bool active = (wave == 0) && (lane < nch);
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab;
+    const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
+    const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
+    const uint32_t ringbuf = (uint32_t)nch * (CDW + 1) * 16u;   // bytes per ring buffer
 
-    // walker registers
-    uint32_t R = 0, C = 0, tA = 0, tB = 0;   // row offsets before / after the last site's move
+    // stage the lattice: lane c's dword d = sites 4d..4d+3 of chain chain0 + c
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        const uint32_t v = (uint32_t)g[0] | ((uint32_t)g[p.C] << 8) | ((uint32_t)g[2 * (int64_t)p.C] << 16) |
+                           ((uint32_t)g[3 * (int64_t)p.C] << 24);
+        lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
+    }
+    __syncthreads();
+
+    const uint32_t sb = spin0 + (uint32_t)(lane * P) * 4u;   // this lane's lattice
+    const uint32_t rb = ring0 + (uint32_t)(lane * (CDW + 1)) * 16u;
+    auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
+
+    uint32_t R = 0, C = 0, tA = 0, tB = 0;
     bool acc = false;
-    int m = 0;
-    FastBulk nb{0, 0, 0};
+    FastBulk nb{0, 0, 0, 0, 0};
     if (active) {
         const int k = p.k[it.chain0 + lane];
-        m = p.m[it.chain0 + lane];
         R = tab0 + 20u * (uint32_t)(k >> 1);
         C = R;
-        nb = fast_bulk(sp, ls, 0, W, NW);
-        // candidates of site 0: left neighbour never flipped yet
-        tA = lds_word(lds, R + 16u - 4u * byte_of(nb.d0, 0));
+        const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
+        nb = fast_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1));
+        tA = lds_ld(R + ubyte(nb.a0, 0));
         tB = tA;
     }
 
-    const int ptid = tid - 64, nprod = nthreads - 64;
-    if (wave > 0) produce_chunk<kIsing>(p, it, ring, 0, nchunks, sweep0, ptid, nprod);
+    // producers: chunk t covers rows (t mod NCH) * RPC .. + RPC - 1 of sweep t / NCH
+    auto produce = [&](int t) {
+        const int sw = t / NCH;
+        const uint32_t sweep = sweep0 + (uint32_t)sw;
+        const int blk0 = (t - sw * NCH) * CDW;   // Philox block of the chunk's first dword
+        const uint32_t buf = ring0 + (uint32_t)(t & 1) * ringbuf;
+        const int total = CDW * nch;
+        for (int w = tid - 64; w < total; w += nthreads - 64) {
+            const int c = w / CDW, q = w - c * CDW;
+            const uint4 b = philox4x32_10((uint32_t)(blk0 + q), sweep, (uint32_t)(it.chain0 + c), 0u, p.seed_lo,
+                                          p.seed_hi);
+            lds_st4(buf + (uint32_t)(c * (CDW + 1) + q) * 16u,
+                    make_uint4(min(b.x, 0xFFFFFFFEu), min(b.y, 0xFFFFFFFEu), min(b.z, 0xFFFFFFFEu),
+                               min(b.w, 0xFFFFFFFEu)));
+        }
+    };
+
+    const int total_chunks = NCH * l.n_sweeps;
+    if (wave > 0) produce(0);
     __syncthreads();
-    int d = 0;   // dword within the sweep
     for (int t = 0; t < total_chunks; ++t) {
         if (wave == 0) {
             if (active) {
-                const uint4 *wr = wring + (t & 1) * (kChunkSites / 4) * ls;
-#pragma unroll 1
-                for (int q4 = 0; q4 < kChunkSites / 4; ++q4) {
-                    const FastBulk b = nb;
-                    const int dn = (d + 1 == NW) ? 0 : d + 1;
-                    nb = fast_bulk(sp, ls, dn, W, NW);
-                    const uint4 u = wr[q4 * ls];
-                    uint32_t fb = 0;
+                const int ci = t % NCH;                 // chunk within the sweep
+                const uint32_t ub = rb + (uint32_t)(t & 1) * ringbuf;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        // row before this site's move, and this site's candidate count
-                        const uint32_t Rj = acc ? C : R;
-                        const uint32_t Dj = acc ? byte_of(b.d1, j) : byte_of(b.d0, j);
-                        const uint32_t Cj = Rj + 40u - 20u * Dj;
-                        // table words of the next site for both outcomes of this one
-                        const uint32_t a0 = (j < 3) ? byte_of(b.d0, j + 1) : byte_of(nb.d0, 0);
-                        const uint32_t a1 = (j < 3) ? byte_of(b.d1, j + 1) : byte_of(nb.d1, 0);
-                        const uint32_t nA = lds_word(lds, Rj + 16u - 4u * a0);
-                        const uint32_t nB = lds_word(lds, Cj + 16u - 4u * a1);
-                        const uint32_t tj = acc ? tB : tA;
-                        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
-                        acc = uj < tj;
-                        fb |= (uint32_t)acc << j;
-                        R = Rj;
-                        C = Cj;
-                        tA = nA;
-                        tB = nB;
+                for (int r = 0; r < RPC; ++r) {
+                    const int y = ci * RPC + r;
+                    const uint32_t vcur = row_addr(y);
+                    // rows of the next row's bulk (wrapping into the next sweep)
+                    const int yn = (y + 1 == L) ? 0 : y + 1;
+                    const uint32_t vnc = row_addr(yn);
+                    const uint32_t vnd = row_addr(yn + 1 == L ? 0 : yn + 1);
+                    const uint32_t vup = row_addr(y == 0 ? L - 1 : y - 1);
+                    const uint32_t vdn = vnc;
+                    uint32_t nxt_cache = lds_ld(vcur + 4);   // old dword 1
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const FastBulk b = nb;
+                        // bulk of the next dword
+                        if (w + 1 < W) {
+                            const uint32_t c1 = nxt_cache;   // old dword w+1
+                            const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                            nb = fast_bulk<false>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)), lds_ld(vdn + 4 * (w + 1)));
+                            nxt_cache = c2;
+                        } else {
+                            // first dword of the next row: its upper row is this one (new)
+                            nb = fast_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
+                                                 lds_ld(vnd));
+                        }
+                        const uint4 u = lds_ld4(ub + (uint32_t)(r * W + w) * 16u);
+                        uint32_t fb = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t Rj = acc ? C : R;
+                            const int32_t Ej = acc ? sbyte(b.e1, j) : sbyte(b.e0, j);
+                            const uint32_t Cj = Rj + (uint32_t)Ej;
+                            const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
+                            const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
+                            const uint32_t nA = lds_ld(Rj + a0);
+                            const uint32_t nB = lds_ld(Cj + a1);
+                            const uint32_t tj = acc ? tB : tA;
+                            const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+                            acc = uj < tj;
+                            fb = fb + fb + (uint32_t)acc;
+                            R = Rj;
+                            C = Cj;
+                            tA = nA;
+                            tB = nB;
+                        }
+                        // fb: bit 3 = site 0 ... bit 0 = site 3; spread to bytes, reverse
+                        const uint32_t spread = (fb * 0x204081u) & 0x01010101u;
+                        lds_st(vcur + 4 * w, b.cur ^ __builtin_amdgcn_perm(spread, spread, 0x00010203u));
                     }
-                    const uint32_t flips = (fb * 0x204081u) & 0x01010101u;
-                    if (l.record == kRecProd) {
-                        // each flip of a 0 adds 2 to M, each flip of a 1 subtracts 2
-                        const int nflip = __builtin_popcount(fb);
-                        const int nflip1 = __builtin_popcount(flips & b.cur);
-                        m += 2 * (nflip - 2 * nflip1);
-                    }
-                    sp[d * ls] = b.cur ^ flips;
-                    d = dn;
-                    if (d == 0 && l.record != kRecNone) {
+                    if (y == L - 1 && l.record != kRecNone) {
                         const uint32_t Rk = acc ? C : R;
                         const int k = 2 * (int)((Rk - tab0) / 20u);
-                        const int c = it.chain0 + lane;
-                        p.hist[(int64_t)k * p.C + c] += 1;
-                        if (l.record == kRecProd) p.sabs[(int64_t)k * p.C + c] += (int64_t)(m < 0 ? -m : m);
+                        const int64_t cidx = (int64_t)k * p.C + it.chain0 + lane;
+                        g_i32 *h = (g_i32 *)p.hist;
+                        h[cidx] += 1;
+                        if (l.record == kRecProd) {
+                            int ones = 0;
+                            for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
+                            const int m = 2 * ones - L * L;
+                            g_i64 *s = (g_i64 *)p.sabs;
+                            s[cidx] += (int64_t)(m < 0 ? -m : m);
+                        }
                     }
                 }
             }
         } else if (t + 1 < total_chunks) {
-            produce_chunk<kIsing>(p, it, ring, t + 1, nchunks, sweep0, ptid, nprod);
+            produce(t + 1);
         }
         __syncthreads();
     }
@@ -425,10 +512,31 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     if (active) {
         const uint32_t Rk = acc ? C : R;
         p.k[it.chain0 + lane] = 2 * (int)((Rk - tab0) / 20u);
-        // magnetisation from the lattice (tracked only while producing)
         int ones = 0;
-        for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(sp[dd * ls]);
-        p.m[it.chain0 + lane] = 2 * ones - p.N;
+        for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
+        p.m[it.chain0 + lane] = 2 * ones - L * L;
+    }
+    __syncthreads();
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint32_t v = lds_ld(spin0 + (uint32_t)(c * P + d) * 4u);
+        uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        g[0] = (uint8_t)v;
+        g[p.C] = (uint8_t)(v >> 8);
+        g[2 * (int64_t)p.C] = (uint8_t)(v >> 16);
+        g[3 * (int64_t)p.C] = (uint8_t)(v >> 24);
+    }
+}
+
+__device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
+                                                      const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
+    switch (p.L) {
+    case 16: run_ising_fast<16>(p, it, lds, l, sweep0, plan); return true;
+    case 24: run_ising_fast<24>(p, it, lds, l, sweep0, plan); return true;
+    case 32: run_ising_fast<32>(p, it, lds, l, sweep0, plan); return true;
+    case 48: run_ising_fast<48>(p, it, lds, l, sweep0, plan); return true;
+    case 64: run_ising_fast<64>(p, it, lds, l, sweep0, plan); return true;
+    default: return false;
     }
 }
 
@@ -450,6 +558,9 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
         for (int j = tid; j < n; j += nthreads) t[j] = p.table[j];
         tab = t;
     }
+    if (MODEL == kIsing && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
+        if (run_fast_if_supported(p, it, lds, l, sweep0, plan)) return;
+    }
     SpinRef<SPIN_LDS> S;
     const int ls = it.spin_stride;
     if (SPIN_LDS) {
@@ -467,10 +578,7 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
     }
     uint4 *ring = reinterpret_cast<uint4 *>(lds + plan.off_ring);
 
-    if (MODEL == kIsing && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
-        __syncthreads();
-        run_ising_fast(p, it, lds, l, sweep0, plan);
-    } else {
+    {
         const int nchunks = (p.N + kChunkSites - 1) / kChunkSites;
         const int total_chunks = nchunks * l.n_sweeps;
         const bool active = (wave == 0) && (lane < it.nchains);
