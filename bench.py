@@ -1,12 +1,15 @@
 """Benchmark: spin-update throughput of the multicanonical weight iteration.
 
-One step is one weight iteration of the 2D Ising L = 64 workload with 4096
-chains: 2000 recorded sweeps of every chain (the sweep kernel), the merge of
-the per-chain histograms, the recursion lnW <- lnW - ln H and the rebuilt
-acceptance tables.  Inputs (spins, tables) are resident in HBM before the
-timed region.  Prints one JSON line.
+One step is one weight iteration: every chain runs the iteration's recorded
+sweeps (the sweep kernel), the per-chain histograms are merged, the
+recursion lnW <- lnW - ln H is applied and the acceptance tables are
+rebuilt.  The default workload is 2D Ising L = 64 with 4096 chains and 2000
+sweeps per iteration; --workload potts32 (8-state Potts L = 32, 4096 chains,
+5000 sweeps) and --workload mixed (nine problems of 512 chains in one launch,
+2000 sweeps) measure the other configurations.  Inputs (spins, tables) are
+resident in HBM before the timed region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload ising64|potts32|mixed]
 """
 import argparse
 import hashlib
@@ -64,7 +67,8 @@ def cpu_baseline(prob, sweeps: int, n_chains: int):
     dt = time.perf_counter() - t0
     ups = n_chains * sweeps * prob.N / dt
     return {"value": round(ups / 1e9, 4), "unit": "G/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_chains} chains x {sweeps} recorded sweeps of Ising L={prob.L} "
+            "sample": f"{n_chains} chains x {sweeps} recorded sweeps of "
+                      f"{'Ising' if prob.model == 0 else str(prob.q) + '-state Potts'} L={prob.L} "
                       f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
 
 
@@ -76,6 +80,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rng-mode", type=int, default=0)
     ap.add_argument("--chains-per-wg", type=int, default=0)
+    ap.add_argument("--fixed", action="store_true",
+                    help="skip tuning: 16 chains per workgroup, 3 producer waves, LDS placement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the production and reweighting leg")
+    ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed"])
+    ap.add_argument("--graph", action="store_true", help="run each iteration as one HIP graph launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by chains "
@@ -84,67 +93,89 @@ def main():
 
     import torch
     import paper_1212_3975_amd as pm
-    from workloads import C2
+    from workloads import C2, C3, C4
 
-    prob = C2.problems[0]
-    M = C2.sweeps_per_iter
+    plan = {"ising64": C2, "potts32": C3, "mixed": C4}[args.workload]
+    probs = list(plan.problems)
+    prob = probs[0]
+    M = plan.sweeps_per_iter
     torch.cuda.set_device(0)
-    ctx = pm.Muca([prob], device="cuda:0", rng_mode=args.rng_mode, chains_per_wg=args.chains_per_wg)
-    launch = ctx.launch_info()
-    updates_per_step = prob.n_chains * prob.N * M
+    opts = dict(rng_mode=args.rng_mode, chains_per_wg=args.chains_per_wg, use_graph=int(args.graph))
+    if args.fixed:
+        opts.update(rng_mode=4, chains_per_wg=16, spin_placement=1, table_placement=1)
+    ctx = pm.Muca(probs, device="cuda:0", **opts)
+    launch = [ctx.launch_info(i) for i in range(len(probs))]
+    updates_per_step = sum(p.n_chains * p.N for p in probs) * M
+    ops_per_update = OPS_PER_ISING_UPDATE if args.workload == "ising64" else None
+
+    def step():
+        if args.graph:
+            return ctx.iterate(M)
+        ctx.sweep(M, pm.REC_MUCA)
+        return ctx.merge_update(True)
 
     for _ in range(args.warmup):
-        ctx.sweep(M, pm.REC_MUCA)
-        ctx.merge_update(True)
+        step()
     ctx.sweep_timing()   # reset kernel timing to the timed region
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
     for _ in range(args.steps):
-        ctx.sweep(M, pm.REC_MUCA)
-        stats = ctx.merge_update(True)[0]
+        stats = step()[0]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     avg_ms, n_launch = ctx.sweep_timing()
 
     value = updates_per_step * args.steps / dt / 1e9
-    achieved = OPS_PER_ISING_UPDATE * updates_per_step / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
     kernel_rate = updates_per_step / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    if ops_per_update is None:
+        # Potts: half a Philox block (40 ops) plus the update (8 compares,
+        # 6 adds, proposal 3, table index 2, compare 1, state 2) = 62
+        ops_per_update = 62 if args.workload == "potts32" else None
+    achieved = (ops_per_update or 0) * updates_per_step / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
 
-    # production and reweighting leg (reported, not part of the value)
-    ctx.clear_production()
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    ctx.sweep(200, pm.REC_PROD)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - tp
-    tr = time.perf_counter()
-    ctx.reweight(0, C2.betas)
-    tr = time.perf_counter() - tr
+    extra = {}
+    if not args.no_extra and args.workload == "ising64":
+        # production and reweighting leg (reported, not part of the value)
+        ctx.clear_production()
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        ctx.sweep(200, pm.REC_PROD)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        tr = time.perf_counter()
+        ctx.reweight(0, C2.betas)
+        tr = time.perf_counter() - tr
+        extra = {"production_Gups": round(prob.n_chains * prob.N * 200 / tp / 1e9, 3),
+                 "reweight_ms_200_betas": round(tr * 1e3, 3)}
+    workload_text = {
+        "ising64": "2D Ising L=64 periodic, 4096 chains, one weight iteration of 2000 sweeps "
+                   "(sweep + merge + recursion + tables)",
+        "potts32": "2D 8-state Potts L=32 periodic, 4096 chains, one weight iteration of 5000 sweeps "
+                   "(sweep + merge + recursion + tables)",
+        "mixed": "Ising L in {16,24,32,48,64} and 8-Potts L in {8,16,24,32}, 512 chains each, one launch, "
+                 "one weight iteration of 2000 sweeps",
+    }[args.workload]
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "G/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "2D Ising L=64 periodic, 4096 chains, one weight iteration of 2000 sweeps "
-                               "(sweep + merge + recursion + tables)",
-                   "L": prob.L, "chains": prob.n_chains, "sweeps_per_iter": M, "seed": prob.seed,
-                   "launch": launch},
+        "config": {"workload": workload_text, "problems": [(p.model, p.L, p.n_chains, p.seed) for p in probs],
+                   "sweeps_per_iter": M, "graph": bool(args.graph), "launch": launch},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_INT32_OPS / 1e12, 2),
                      "unit": "Tops/s (int32 lane ops)", "frac": round(achieved / PEAK_INT32_OPS, 5),
-                     "traffic": measured_traffic(updates_per_step),
+                     "traffic": measured_traffic(updates_per_step) if args.workload == "ising64" else None,
                      "kernel": "sweep_kernel", "kernel_avg_ms": round(avg_ms, 3), "kernel_launches": n_launch,
-                     "kernel_rate_Gups": round(kernel_rate, 3), "ops_per_update": OPS_PER_ISING_UPDATE},
-        "extra": {"production_Gups": round(prob.n_chains * prob.N * 200 / tp / 1e9, 3),
-                  "reweight_ms_200_betas": round(tr * 1e3, 3),
-                  "last_iter": {k: stats[k] for k in ("k_lo", "k_hi", "visited", "reachable", "flat")},
-                  "kernel_source_hash": kernel_source_hash()},
+                     "kernel_rate_Gups": round(kernel_rate, 3), "ops_per_update": ops_per_update},
+        "extra": dict(extra, last_iter={k: stats[k] for k in ("k_lo", "k_hi", "visited", "reachable", "flat")},
+                      kernel_source_hash=kernel_source_hash()),
     }
     ctx.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, 2000, 128)
+        out["cpu_baseline"] = cpu_baseline(prob, 2000, 128 if prob.model == 0 else 256)
     print(json.dumps(out), flush=True)
 
 

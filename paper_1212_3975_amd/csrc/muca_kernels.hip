@@ -91,6 +91,7 @@ struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
 };
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves);
+__host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves);
 __host__ __device__ constexpr int fast_rows_per_chunk(int L) { return (64 + L - 1) / L; }
 __host__ __device__ constexpr int fast_lane_stride(int L) { return ((L * L / 4) % 2) ? L * L / 4 : L * L / 4 + 1; }
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
@@ -104,6 +105,15 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
         const int cdw = fast_rows_per_chunk(p.L) * W;
         l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
         l.total = l.off_ring + 2 * it.nchains * (cdw + 1) * 16;
+        return l;
+    }
+    if (fast_potts_ok(p, n_producer_waves)) {
+        // lane-major lattice; ring of three buffers: [3][lane][chunk dwords + 1] uint4 words
+        // followed by [3][lane][chunk dwords + 1] packed proposal offsets
+        const int W = p.L / 4;
+        const int cdw = fast_rows_per_chunk(p.L) * W;
+        l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
+        l.total = l.off_ring + 3 * it.nchains * (cdw + 1) * 20;
         return l;
     }
     const int spn = p.spin_lds ? round_up((p.N + 3) / 4 * it.spin_stride * 4, 16) : 0;
@@ -124,8 +134,15 @@ __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_w
     const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32 || p.L == 48 || p.L == 64;
     return p.model == kIsing && size_ok && p.spin_lds && p.table_lds && n_producer_waves > 0;
 }
+// The fast Potts walker: q = 8, compiled sizes, both arrays in LDS, producers.
+__host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves) {
+    const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32;
+    return p.model == kPotts && p.q == 8 && size_ok && p.spin_lds && p.table_lds && n_producer_waves > 0;
+}
 
-bool uses_fast_walker(const ProbDev &p, int n_producer_waves) { return fast_ising_ok(p, n_producer_waves); }
+bool uses_fast_walker(const ProbDev &p, int n_producer_waves) {
+    return fast_ising_ok(p, n_producer_waves) || fast_potts_ok(p, n_producer_waves);
+}
 
 template <bool LDS>
 struct SpinRef {
@@ -540,6 +557,235 @@ __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const Wo
     }
 }
 
+// ------------------------------------------------------------------ fast Potts walker (q = 8)
+//
+// Same scheme as the fast Ising walker.  Per dword of four sites the bulk
+// step forms the proposals s' = (s + 1 + t) mod 8 and, with byte-wise xor and
+// a v_perm lookup that maps 0 to 1 and 1..7 to 0, the equalities of every
+// neighbour with s and with s'.  The energy change of a site is
+// dk = sum_nb ([nb = s] - [nb = s']); the left neighbour's term has two
+// candidates (its old state, or its proposal if it was accepted).  Bytes hold
+// dk as int8 (for the row step, 36 bytes per row of nine columns) and the
+// column byte offset 16 + 4 dk.  Proposal offsets are needed one dword ahead
+// of the walker, across chunk boundaries, so the ring has three buffers and
+// the producers run two chunks ahead.
+
+struct PottsBulk {
+    uint32_t cur;      // old states
+    uint32_t sp;       // proposals
+    uint32_t a0, a1;   // bytes: column byte offset for candidates 0 / 1
+    uint32_t k0, k1;   // bytes (int8): dk for candidates 0 / 1
+};
+
+__device__ __forceinline__ uint32_t eq8(uint32_t a, uint32_t b) {
+    // per byte: 1 if equal (values 0..7), else 0
+    return __builtin_amdgcn_perm(0u, 0x00000001u, a ^ b);
+}
+
+template <bool ROW_START>
+__device__ __forceinline__ PottsBulk potts_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn,
+                                                uint32_t tq4, uint32_t sp_prv) {
+    PottsBulk b;
+    b.cur = cur;
+    b.sp = (cur + 0x01010101u + tq4) & 0x07070707u;
+    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
+    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);        // left, old state
+    const uint32_t ln = __builtin_amdgcn_alignbyte(b.sp, sp_prv, 3);    // left, its proposal
+    const uint32_t P = eq8(up, cur) + eq8(dn, cur) + eq8(rn, cur);
+    const uint32_t Q = eq8(up, b.sp) + eq8(dn, b.sp) + eq8(rn, b.sp);
+    const uint32_t X0 = P + eq8(lo, cur), Y0 = Q + eq8(lo, b.sp);
+    uint32_t X1 = P + eq8(ln, cur), Y1 = Q + eq8(ln, b.sp);
+    if (ROW_START) {
+        // the first site's left neighbour (row end) has not been visited yet
+        X1 = (X1 & 0xFFFFFF00u) | (X0 & 0xFFu);
+        Y1 = (Y1 & 0xFFFFFF00u) | (Y0 & 0xFFu);
+    }
+    // dk = X - Y in [-4, 4]: biased bytes 0x80 + dk never borrow
+    const uint32_t b0 = (X0 | 0x80808080u) - Y0, b1 = (X1 | 0x80808080u) - Y1;
+    b.k0 = b0 ^ 0x80808080u;
+    b.k1 = b1 ^ 0x80808080u;
+    // column offset 4 (dk + 4) = 4 ((0x80 + dk) - 0x7c)
+    b.a0 = (b0 - 0x7C7C7C7Cu) << 2;
+    b.a1 = (b1 - 0x7C7C7C7Cu) << 2;
+    return b;
+}
+
+template <int L>
+__device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                               uint32_t sweep0, const LdsPlan &plan) {
+    constexpr int W = L / 4;
+    constexpr int NW = L * L / 4;
+    constexpr int RPC = fast_rows_per_chunk(L);
+    constexpr int CDW = RPC * W;
+    constexpr int NCH = L / RPC;
+    constexpr int P = fast_lane_stride(L);
+    constexpr uint32_t ROWB = 36u;            // table row: nine words
+    static_assert(L % RPC == 0 && W >= 4, "fast walker shape");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthreads = blockDim.x;
+    const int nch = it.nchains;
+    const bool active = (wave == 0) && (lane < nch);
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab;
+    const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
+    const uint32_t ringu0 = lbase + (uint32_t)plan.off_ring;                    // [3][lane][CDW+1] uint4
+    const uint32_t ubuf = (uint32_t)nch * (CDW + 1) * 16u;
+    const uint32_t ringt0 = ringu0 + 3u * ubuf;                                 // [3][lane][CDW+1] uint32
+    const uint32_t tbuf = (uint32_t)nch * (CDW + 1) * 4u;
+
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        const uint32_t v = (uint32_t)g[0] | ((uint32_t)g[p.C] << 8) | ((uint32_t)g[2 * (int64_t)p.C] << 16) |
+                           ((uint32_t)g[3 * (int64_t)p.C] << 24);
+        lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
+    }
+
+    // producers: chunk t covers rows (t mod NCH) * RPC .. + RPC - 1 of sweep t / NCH;
+    // one work unit is one dword (two Philox blocks of two sites each)
+    auto produce = [&](int t) {
+        const int sw = t / NCH;
+        const uint32_t sweep = sweep0 + (uint32_t)sw;
+        const int dw0 = (t - sw * NCH) * CDW;
+        const uint32_t bu = ringu0 + (uint32_t)(t % 3) * ubuf, bt = ringt0 + (uint32_t)(t % 3) * tbuf;
+        const int total = CDW * nch;
+        for (int w = tid - 64; w < total; w += nthreads - 64) {
+            const int c = w / CDW, q = w - c * CDW;
+            const uint32_t chain = (uint32_t)(it.chain0 + c);
+            const uint4 b0 = philox4x32_10((uint32_t)(2 * (dw0 + q)), sweep, chain, 0u, p.seed_lo, p.seed_hi);
+            const uint4 b1 = philox4x32_10((uint32_t)(2 * (dw0 + q) + 1), sweep, chain, 0u, p.seed_lo, p.seed_hi);
+            const uint32_t t0 = (uint32_t)(((uint64_t)b0.x * 7u) >> 32), t1 = (uint32_t)(((uint64_t)b0.z * 7u) >> 32);
+            const uint32_t t2 = (uint32_t)(((uint64_t)b1.x * 7u) >> 32), t3 = (uint32_t)(((uint64_t)b1.z * 7u) >> 32);
+            const uint32_t off = (uint32_t)(c * (CDW + 1) + q);
+            lds_st4(bu + off * 16u, make_uint4(min(b0.y, 0xFFFFFFFEu), min(b0.w, 0xFFFFFFFEu),
+                                               min(b1.y, 0xFFFFFFFEu), min(b1.w, 0xFFFFFFFEu)));
+            lds_st(bt + off * 4u, t0 | (t1 << 8) | (t2 << 16) | (t3 << 24));
+        }
+    };
+
+    const int total_chunks = NCH * l.n_sweeps;
+    if (wave > 0) {
+        produce(0);
+        if (total_chunks > 1) produce(1);
+    }
+    __syncthreads();
+
+    const uint32_t sb = spin0 + (uint32_t)(lane * P) * 4u;
+    const uint32_t rbu = ringu0 + (uint32_t)(lane * (CDW + 1)) * 16u;
+    const uint32_t rbt = ringt0 + (uint32_t)(lane * (CDW + 1)) * 4u;
+    auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
+
+    uint32_t R = 0, C = 0, tA = 0, tB = 0;
+    bool acc = false;
+    PottsBulk nb{0, 0, 0, 0, 0, 0};
+    if (active) {
+        const int k = p.k[it.chain0 + lane];
+        R = tab0 + ROWB * (uint32_t)k;
+        C = R;
+        const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
+        nb = potts_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1),
+                              lds_ld(rbt), 0u);
+        tA = lds_ld(R + ubyte(nb.a0, 0));
+        tB = tA;
+    }
+
+    for (int t = 0; t < total_chunks; ++t) {
+        if (wave == 0) {
+            if (active) {
+                const int ci = t % NCH;
+                const uint32_t ub = rbu + (uint32_t)(t % 3) * ubuf;
+                const uint32_t tb = rbt + (uint32_t)(t % 3) * tbuf;
+                const uint32_t tbn = rbt + (uint32_t)((t + 1) % 3) * tbuf;   // next chunk's offsets
+#pragma unroll
+                for (int r = 0; r < RPC; ++r) {
+                    const int y = ci * RPC + r;
+                    const uint32_t vcur = row_addr(y);
+                    const int yn = (y + 1 == L) ? 0 : y + 1;
+                    const uint32_t vnc = row_addr(yn);
+                    const uint32_t vnd = row_addr(yn + 1 == L ? 0 : yn + 1);
+                    const uint32_t vup = row_addr(y == 0 ? L - 1 : y - 1);
+                    const uint32_t vdn = vnc;
+                    uint32_t nxt_cache = lds_ld(vcur + 4);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const PottsBulk b = nb;
+                        if (w + 1 < W) {
+                            const uint32_t c1 = nxt_cache;
+                            const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                            nb = potts_bulk<false>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)), lds_ld(vdn + 4 * (w + 1)),
+                                                   lds_ld(tb + (uint32_t)(r * W + w + 1) * 4u), b.sp);
+                            nxt_cache = c2;
+                        } else {
+                            const uint32_t tq = (r + 1 < RPC) ? lds_ld(tb + (uint32_t)((r + 1) * W) * 4u) : lds_ld(tbn);
+                            nb = potts_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
+                                                  lds_ld(vnd), tq, 0u);
+                        }
+                        const uint4 u = lds_ld4(ub + (uint32_t)(r * W + w) * 16u);
+                        uint32_t fb = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t Rj = acc ? C : R;
+                            const int32_t dk = acc ? sbyte(b.k1, j) : sbyte(b.k0, j);
+                            const uint32_t Cj = (uint32_t)((int32_t)Rj + (int32_t)ROWB * dk);
+                            const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
+                            const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
+                            const uint32_t nA = lds_ld(Rj + a0);
+                            const uint32_t nB = lds_ld(Cj + a1);
+                            const uint32_t tj = acc ? tB : tA;
+                            const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+                            acc = uj < tj;
+                            fb = fb + fb + (uint32_t)acc;
+                            R = Rj;
+                            C = Cj;
+                            tA = nA;
+                            tB = nB;
+                        }
+                        const uint32_t spread = __builtin_amdgcn_perm(0u, (fb * 0x204081u) & 0x01010101u, 0x00010203u);
+                        const uint32_t mask = (spread << 8) - spread;   // 0xff bytes where accepted
+                        lds_st(vcur + 4 * w, (mask & b.sp) | (~mask & b.cur));
+                    }
+                    if (y == L - 1 && l.record != kRecNone) {
+                        const uint32_t Rk = acc ? C : R;
+                        const int k = (int)((Rk - tab0) / ROWB);
+                        g_i32 *h = (g_i32 *)p.hist;
+                        h[(int64_t)k * p.C + it.chain0 + lane] += 1;
+                    }
+                }
+            }
+        } else if (t + 2 < total_chunks) {
+            produce(t + 2);
+        }
+        __syncthreads();
+    }
+
+    if (active) {
+        const uint32_t Rk = acc ? C : R;
+        p.k[it.chain0 + lane] = (int)((Rk - tab0) / ROWB);
+        p.m[it.chain0 + lane] = 0;
+    }
+    __syncthreads();
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint32_t v = lds_ld(spin0 + (uint32_t)(c * P + d) * 4u);
+        uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        g[0] = (uint8_t)v;
+        g[p.C] = (uint8_t)(v >> 8);
+        g[2 * (int64_t)p.C] = (uint8_t)(v >> 16);
+        g[3 * (int64_t)p.C] = (uint8_t)(v >> 24);
+    }
+}
+
+__device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
+                                                            const SweepLaunch &l, uint32_t sweep0,
+                                                            const LdsPlan &plan) {
+    switch (p.L) {
+    case 16: run_potts_fast<16>(p, it, lds, l, sweep0, plan); return true;
+    case 24: run_potts_fast<24>(p, it, lds, l, sweep0, plan); return true;
+    case 32: run_potts_fast<32>(p, it, lds, l, sweep0, plan); return true;
+    default: return false;
+    }
+}
+
 // ------------------------------------------------------------------ work item driver
 
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
@@ -560,6 +806,9 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
     }
     if (MODEL == kIsing && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
         if (run_fast_if_supported(p, it, lds, l, sweep0, plan)) return;
+    }
+    if (MODEL == kPotts && SPIN_LDS && TAB_LDS && fast_potts_ok(p, l.n_producer_waves)) {
+        if (run_potts_fast_if_supported(p, it, lds, l, sweep0, plan)) return;
     }
     SpinRef<SPIN_LDS> S;
     const int ls = it.spin_stride;

@@ -95,7 +95,8 @@ CONFIGS = [dict(rng_mode=1, chains_per_wg=16, spin_placement=1, table_placement=
 @pytest.mark.parametrize("prob", [Problem(ISING, 6, 100, 7), Problem(POTTS, 3, 70, 8, q=8),
                                   Problem(POTTS, 7, 41, 9, q=8), Problem(ISING, 12, 65, 10),
                                   Problem(POTTS, 9, 20, 11, q=3), Problem(ISING, 16, 40, 12),
-                                  Problem(ISING, 24, 33, 13)],
+                                  Problem(ISING, 24, 33, 13), Problem(POTTS, 16, 40, 14, q=8),
+                                  Problem(POTTS, 24, 21, 15, q=8)],
                          ids=lambda p: f"{'ising' if p.model == 0 else 'potts'}L{p.L}C{p.n_chains}")
 def test_launch_configurations_bit_exact(prob, cfg):
     """Ragged chain counts, lattices that end inside a chunk, every random-number
@@ -104,8 +105,10 @@ def test_launch_configurations_bit_exact(prob, cfg):
     print("case", prob, cfg, flush=True)
     with pm.Muca([prob], **cfg) as ctx:
         info = ctx.launch_info()
-        fast_expected = (prob.model == ISING and prob.L % 8 == 0 and prob.L >= 16 and cfg["rng_mode"] > 1
-                         and cfg["spin_placement"] == 1 and cfg["table_placement"] == 1)
+        placed = cfg["rng_mode"] > 1 and cfg["spin_placement"] == 1 and cfg["table_placement"] == 1
+        fast_shape = ((prob.model == ISING and prob.L in (16, 24, 32, 48, 64)) or
+                      (prob.model == POTTS and prob.q == 8 and prob.L in (16, 24, 32)))
+        fast_expected = placed and fast_shape
         assert info["fast_walker"] == int(fast_expected), info
         orc = _orc(prob)
         _compare_iterations(ctx, orc, 4, 150)
