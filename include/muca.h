@@ -200,6 +200,51 @@ muca_status mucaSweepTiming(muca_ctx ctx, double *avg_ms, int32_t *n_launches);
 muca_status mucaCheckpoint(muca_ctx ctx, void *blob, size_t *bytes);
 muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes);
 
+/* The problem definition of index prob (as validated, q = 2 for Ising). */
+muca_status mucaProblemInfo(muca_ctx ctx, int32_t prob, muca_problem *out);
+
+/* ---------------------------------------------------------------------
+ * Learned initial weights.  An MLP 4 -> 64 -> 64 -> 64 -> 1 with tanh-form
+ * GELU maps (Ising one-hot, Potts one-hot, 8/L, E/N) to ln Omega(E)/N.  Its
+ * weights are BF16 in the matrix products with FP32 accumulation; FP32
+ * master weights are updated by Adam (full batch, MSE loss).  Training data
+ * come from weights the recursion converged to at small L: with a flat
+ * histogram W = 1/Omega up to a constant (Sec. 2), fixed here by
+ * sum_E Omega(E) = q^N.  The prediction seeds lnW = -N f(...) at larger L;
+ * the recursion then continues from there.
+ * --------------------------------------------------------------------- */
+typedef struct muca_mlp_s *muca_mlp;
+
+/* Workspace bytes for up to max_samples training samples (1..2^22). */
+muca_status mucaMlpWorkspaceSize(int32_t max_samples, size_t *bytes);
+/* Creates the network with seeded uniform(+-1/sqrt(fan_in)) weights.  The
+ * workspace (caller-owned device memory, 256-byte aligned) must outlive it. */
+muca_status mucaMlpCreate(muca_mlp *out, int32_t max_samples, uint64_t seed, void *d_workspace, size_t ws_bytes,
+                          void *hip_stream);
+/* FP32 master parameters (8705 floats: W1[64][4], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], W4[64], b4); setting them also resets Adam. */
+muca_status mucaMlpSetParams(muca_mlp m, const float *params);
+muca_status mucaMlpGetParams(muca_mlp m, float *params);
+/* Training set: raw (x[n][4], y[n]) pairs, or every reachable bin of a
+ * problem's current weights (features as above, target ln Omega / N). */
+muca_status mucaMlpClearData(muca_mlp m);
+muca_status mucaMlpAddData(muca_mlp m, const float *x, const float *y, int32_t n);
+muca_status mucaMlpAddWeights(muca_mlp m, muca_ctx ctx, int32_t prob);
+muca_status mucaMlpNumSamples(muca_mlp m, int32_t *n);
+/* steps full-batch Adam steps (beta 0.9/0.999, eps 1e-8) at rate lr;
+ * loss_out (host, steps floats, may be NULL) gets each step's MSE. */
+muca_status mucaMlpTrain(muca_mlp m, int32_t steps, float lr, float *loss_out);
+/* Gradient of the MSE on the training set at the current parameters
+ * (8705 floats) and the loss, without updating anything. */
+muca_status mucaMlpGradients(muca_mlp m, float *grad, float *loss);
+/* Predictions for n inputs x[n][4] into y[n] (host arrays). */
+muca_status mucaMlpPredict(muca_mlp m, const float *x, int32_t n, float *y);
+/* Installs lnW[k] = -N f(model, 8/L, E_k/N) on the reachable bins of
+ * problem prob (0 elsewhere) through mucaSetLogWeights. */
+muca_status mucaMlpSetLogWeights(muca_mlp m, muca_ctx ctx, int32_t prob);
+void mucaMlpDestroy(muca_mlp m);
+const char *mucaMlpLastError(muca_mlp m);
+
 /* Frees the context (not the workspace).  Safe on NULL. */
 void mucaDestroy(muca_ctx ctx);
 

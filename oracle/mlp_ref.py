@@ -1,0 +1,87 @@
+"""Reference MLP for the learned initial weights -- TEST INFRASTRUCTURE ONLY.
+
+Plain numpy in float64: 4 -> 64 -> 64 -> 64 -> 1 with the tanh form of GELU
+(Hendrycks and Gimpel), MSE loss and its gradient by the chain rule.  With
+rounding on, every matrix-product input (inputs, weights, biases,
+activations and back-propagated pre-activation gradients) is rounded to
+bfloat16 (round to nearest even, through float32) at the same points as the
+HIP kernels; with rounding off the function is the exact float64 network,
+whose gradient a finite-difference check pins.
+
+Parameter vector layout (8705 floats): W1[64][4], b1[64], W2[64][64], b2[64],
+W3[64][64], b3[64], W4[64], b4[1].
+"""
+import numpy as np
+
+N_PARAMS = 8705
+_C = np.sqrt(2.0 / np.pi)
+
+
+def bf16(a):
+    """Round to bfloat16 (nearest even) through float32; returns float64."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def unpack(p):
+    p = np.asarray(p, np.float64)
+    return dict(W1=p[0:256].reshape(64, 4), b1=p[256:320], W2=p[320:4416].reshape(64, 64), b2=p[4416:4480],
+                W3=p[4480:8576].reshape(64, 64), b3=p[8576:8640], W4=p[8640:8704], b4=p[8704:8705])
+
+
+def pack(d):
+    return np.concatenate([d["W1"].ravel(), d["b1"], d["W2"].ravel(), d["b2"], d["W3"].ravel(), d["b3"],
+                           d["W4"], d["b4"]])
+
+
+def gelu(z):
+    t = np.tanh(_C * (z + 0.044715 * z ** 3))
+    return 0.5 * z * (1.0 + t), 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * _C * (1.0 + 3 * 0.044715 * z * z)
+
+
+def forward(p, x, round_bf16=True):
+    R = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    w = {k: R(v) for k, v in unpack(p).items()}
+    cache = {"x0": R(x)}
+    z1 = cache["x0"] @ w["W1"].T + w["b1"]
+    a1 = R(gelu(z1)[0])
+    z2 = a1 @ w["W2"].T + w["b2"]
+    a2 = R(gelu(z2)[0])
+    z3 = a2 @ w["W3"].T + w["b3"]
+    a3 = R(gelu(z3)[0])
+    y = a3 @ w["W4"] + w["b4"][0]
+    cache.update(z1=z1, z2=z2, z3=z3, a1=a1, a2=a2, a3=a3, w=w)
+    return y, cache
+
+
+def loss_and_grad(p, x, t, round_bf16=True):
+    """MSE loss and its gradient with respect to the parameter vector."""
+    R = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    y, c = forward(p, x, round_bf16)
+    w = c["w"]
+    n = y.shape[0]
+    loss = np.mean((y - t) ** 2)
+    dy = 2.0 * (y - t) / n
+    g = {}
+    g["W4"] = c["a3"].T @ dy
+    g["b4"] = np.array([dy.sum()])
+    G3 = R(dy[:, None] * w["W4"][None, :] * gelu(c["z3"])[1])
+    g["W3"] = G3.T @ c["a2"]
+    g["b3"] = G3.sum(axis=0)
+    G2 = R((G3 @ w["W3"]) * gelu(c["z2"])[1])
+    g["W2"] = G2.T @ c["a1"]
+    g["b2"] = G2.sum(axis=0)
+    G1 = R((G2 @ w["W2"]) * gelu(c["z1"])[1])
+    g["W1"] = G1.T @ c["x0"]
+    g["b1"] = G1.sum(axis=0)
+    return loss, pack(g)
+
+
+def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -20,7 +20,11 @@ GET_H, GET_LNW, GET_T, GET_SPINS, GET_K, GET_M, GET_CHAIN_H, GET_PROD_CNT, GET_P
 
 EXPORTED = ["mucaWorkspaceSize", "mucaInit", "mucaSetLogWeights", "mucaSweep", "mucaMergeUpdate",
             "mucaIterate", "mucaReweight", "mucaClearProduction", "mucaGet", "mucaLaunchInfo",
-            "mucaSweepTiming", "mucaCheckpoint", "mucaRestore", "mucaDestroy", "mucaLastError"]
+            "mucaSweepTiming", "mucaCheckpoint", "mucaRestore", "mucaProblemInfo", "mucaDestroy", "mucaLastError",
+            "mucaMlpWorkspaceSize", "mucaMlpCreate", "mucaMlpSetParams", "mucaMlpGetParams", "mucaMlpClearData",
+            "mucaMlpAddData", "mucaMlpAddWeights", "mucaMlpNumSamples", "mucaMlpTrain", "mucaMlpGradients",
+            "mucaMlpPredict", "mucaMlpSetLogWeights", "mucaMlpDestroy", "mucaMlpLastError"]
+MLP_PARAMS = 8705
 
 
 class MucaError(RuntimeError):
@@ -89,12 +93,30 @@ def lib():
         L.mucaSweepTiming.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.mucaCheckpoint.argtypes = [vp, vp, ctypes.POINTER(sz)]
         L.mucaRestore.argtypes = [vp, vp, sz]
+        L.mucaProblemInfo.argtypes = [vp, i32, PP]
         L.mucaDestroy.argtypes = [vp]
         L.mucaDestroy.restype = None
         L.mucaLastError.argtypes = [vp]
         L.mucaLastError.restype = ctypes.c_char_p
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.mucaMlpWorkspaceSize.argtypes = [i32, ctypes.POINTER(sz)]
+        L.mucaMlpCreate.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64, vp, sz, vp]
+        L.mucaMlpSetParams.argtypes = [vp, fp]
+        L.mucaMlpGetParams.argtypes = [vp, fp]
+        L.mucaMlpClearData.argtypes = [vp]
+        L.mucaMlpAddData.argtypes = [vp, fp, fp, i32]
+        L.mucaMlpAddWeights.argtypes = [vp, vp, i32]
+        L.mucaMlpNumSamples.argtypes = [vp, ctypes.POINTER(i32)]
+        L.mucaMlpTrain.argtypes = [vp, i32, ctypes.c_float, fp]
+        L.mucaMlpGradients.argtypes = [vp, fp, fp]
+        L.mucaMlpPredict.argtypes = [vp, fp, i32, fp]
+        L.mucaMlpSetLogWeights.argtypes = [vp, vp, i32]
+        L.mucaMlpDestroy.argtypes = [vp]
+        L.mucaMlpDestroy.restype = None
+        L.mucaMlpLastError.argtypes = [vp]
+        L.mucaMlpLastError.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("mucaDestroy", "mucaLastError"):
+            if name not in ("mucaDestroy", "mucaLastError", "mucaMlpDestroy", "mucaMlpLastError"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -262,3 +284,98 @@ class Muca:
     def restore(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._c(lib().mucaRestore(self._ctx, ctypes.cast(buf, ctypes.c_void_p), len(blob)))
+
+
+def _check_mlp(rc, m=None):
+    if rc != 0:
+        msg = lib().mucaMlpLastError(m)
+        raise MucaError(f"muca mlp error {rc}: {msg.decode() if msg else ''}")
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Mlp:
+    """The learned-initial-weights network (see include/muca.h)."""
+
+    def __init__(self, max_samples: int = 65536, seed: int = 1, device: str = "cuda:0", stream=None):
+        import torch
+        size = ctypes.c_size_t()
+        _check_mlp(lib().mucaMlpWorkspaceSize(int(max_samples), ctypes.byref(size)))
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        self._m = ctypes.c_void_p()
+        _check_mlp(lib().mucaMlpCreate(ctypes.byref(self._m), int(max_samples), int(seed),
+                                       ctypes.c_void_p(self.workspace.data_ptr()), size.value,
+                                       ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def _c(self, rc):
+        _check_mlp(rc, self._m)
+
+    def close(self):
+        if getattr(self, "_m", None) and self._m.value:
+            lib().mucaMlpDestroy(self._m)
+            self._m = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_params(self, p):
+        a = _f32(p)
+        assert a.size == MLP_PARAMS
+        self._c(lib().mucaMlpSetParams(self._m, _dptr(a, ctypes.c_float)))
+
+    def params(self):
+        out = np.zeros(MLP_PARAMS, np.float32)
+        self._c(lib().mucaMlpGetParams(self._m, _dptr(out, ctypes.c_float)))
+        return out
+
+    def clear_data(self):
+        self._c(lib().mucaMlpClearData(self._m))
+
+    def add_data(self, x, y):
+        x = _f32(x)
+        y = _f32(y)
+        self._c(lib().mucaMlpAddData(self._m, _dptr(x, ctypes.c_float), _dptr(y, ctypes.c_float), y.size))
+
+    def add_weights(self, ctx: "Muca", prob: int = 0):
+        self._c(lib().mucaMlpAddWeights(self._m, ctx._ctx, prob))
+
+    def num_samples(self):
+        n = ctypes.c_int32()
+        self._c(lib().mucaMlpNumSamples(self._m, ctypes.byref(n)))
+        return n.value
+
+    def train(self, steps: int, lr: float):
+        losses = np.zeros(max(steps, 1), np.float32)
+        self._c(lib().mucaMlpTrain(self._m, int(steps), float(lr), _dptr(losses, ctypes.c_float)))
+        return losses[:steps]
+
+    def gradients(self):
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        self._c(lib().mucaMlpGradients(self._m, _dptr(g, ctypes.c_float), _dptr(loss, ctypes.c_float)))
+        return float(loss[0]), g
+
+    def predict(self, x):
+        x = _f32(x)
+        n = x.size // 4
+        y = np.zeros(n, np.float32)
+        self._c(lib().mucaMlpPredict(self._m, _dptr(x, ctypes.c_float), n, _dptr(y, ctypes.c_float)))
+        return y
+
+    def set_log_weights(self, ctx: "Muca", prob: int = 0):
+        self._c(lib().mucaMlpSetLogWeights(self._m, ctx._ctx, prob))

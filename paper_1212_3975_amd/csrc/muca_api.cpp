@@ -1004,6 +1004,14 @@ muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes) {
     return MUCA_OK;
 }
 
+muca_status mucaProblemInfo(muca_ctx ctx, int32_t prob, muca_problem *out) {
+    muca_status st = check_prob(ctx, prob);
+    if (st) return st;
+    if (!out) return MUCA_EINVAL;
+    *out = ctx->probs[prob].def;
+    return MUCA_OK;
+}
+
 void mucaDestroy(muca_ctx ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
