@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the production and reweighting leg")
     ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed"])
     ap.add_argument("--graph", action="store_true", help="run each iteration as one HIP graph launch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of this many MiB (a known-size kernel for "
+                         "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by chains "
@@ -95,6 +98,12 @@ def main():
     import paper_1212_3975_amd as pm
     from workloads import C2, C3, C4
 
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     plan = {"ising64": C2, "potts32": C3, "mixed": C4}[args.workload]
     probs = list(plan.problems)
     prob = probs[0]
