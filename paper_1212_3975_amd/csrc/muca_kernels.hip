@@ -450,6 +450,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     const int total_chunks = NCH * l.n_sweeps;
     if (wave > 0) produce(0);
     __syncthreads();
+    uint4 u_next = make_uint4(0, 0, 0, 0);
     for (int t = 0; t < total_chunks; ++t) {
         if (wave == 0) {
             if (active) {
@@ -469,6 +470,9 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const FastBulk b = nb;
+                        // random words of this dword (prefetched one dword ahead inside the chunk)
+                        const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
+                        if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
                         // bulk of the next dword
                         if (w + 1 < W) {
                             const uint32_t c1 = nxt_cache;   // old dword w+1
@@ -480,8 +484,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                             nb = fast_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
                                                  lds_ld(vnd));
                         }
-                        const uint4 u = lds_ld4(ub + (uint32_t)(r * W + w) * 16u);
-                        uint32_t fb = 0;
+                        uint32_t f[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const uint32_t Rj = acc ? C : R;
@@ -494,15 +497,13 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                             const uint32_t tj = acc ? tB : tA;
                             const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
                             acc = uj < tj;
-                            fb = fb + fb + (uint32_t)acc;
+                            f[j] = acc ? (1u << (8 * j)) : 0u;   // accepted: flip byte j
                             R = Rj;
                             C = Cj;
                             tA = nA;
                             tB = nB;
                         }
-                        // fb: bit 3 = site 0 ... bit 0 = site 3; spread to bytes, reverse
-                        const uint32_t spread = (fb * 0x204081u) & 0x01010101u;
-                        lds_st(vcur + 4 * w, b.cur ^ __builtin_amdgcn_perm(spread, spread, 0x00010203u));
+                        lds_st(vcur + 4 * w, b.cur ^ (f[0] | f[1] | f[2] | f[3]));
                     }
                     if (y == L - 1 && l.record != kRecNone) {
                         const uint32_t Rk = acc ? C : R;
@@ -677,6 +678,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     uint32_t R = 0, C = 0, tA = 0, tB = 0;
     bool acc = false;
+    uint4 u_next = make_uint4(0, 0, 0, 0);
     PottsBulk nb{0, 0, 0, 0, 0, 0};
     if (active) {
         const int k = p.k[it.chain0 + lane];
@@ -720,8 +722,9 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                             nb = potts_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
                                                   lds_ld(vnd), tq, 0u);
                         }
-                        const uint4 u = lds_ld4(ub + (uint32_t)(r * W + w) * 16u);
-                        uint32_t fb = 0;
+                        const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
+                        if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
+                        uint32_t f[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const uint32_t Rj = acc ? C : R;
@@ -734,14 +737,13 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                             const uint32_t tj = acc ? tB : tA;
                             const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
                             acc = uj < tj;
-                            fb = fb + fb + (uint32_t)acc;
+                            f[j] = acc ? (0xFFu << (8 * j)) : 0u;   // accepted: take the proposal's byte
                             R = Rj;
                             C = Cj;
                             tA = nA;
                             tB = nB;
                         }
-                        const uint32_t spread = __builtin_amdgcn_perm(0u, (fb * 0x204081u) & 0x01010101u, 0x00010203u);
-                        const uint32_t mask = (spread << 8) - spread;   // 0xff bytes where accepted
+                        const uint32_t mask = f[0] | f[1] | f[2] | f[3];
                         lds_st(vcur + 4 * w, (mask & b.sp) | (~mask & b.cur));
                     }
                     if (y == L - 1 && l.record != kRecNone) {
