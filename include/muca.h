@@ -84,7 +84,13 @@ typedef struct {
  *   flat_rule        0 = all reachable bins visited and min/max >= flat_ratio;
  *                    1 = all reachable bins visited and every entry within
  *                        [avg/2, 2 avg] (the rule of Sec. 3)
- *   tune_sweeps      sweeps per timed candidate when tuning (default 4) */
+ *   tune_sweeps      sweeps per timed candidate when tuning (default 4)
+ *   correction       1 = after each recursion, continue lnW linearly beyond
+ *                    the sampled region [k_lo, k_hi] (bins with H > 0): below
+ *                    k_lo with the slope between k_lo and the reachable bin L
+ *                    reachable bins inward (or the far edge if the region is
+ *                    narrower), likewise above k_hi (the correction function
+ *                    of Sec. 3) */
 typedef struct {
     int32_t chains_per_wg;
     int32_t rng_mode;
@@ -95,6 +101,8 @@ typedef struct {
     double flat_ratio;
     int32_t flat_rule;
     int32_t tune_sweeps;
+    int32_t correction;
+    int32_t pad;
 } muca_options;
 
 /* Statistics of one weight iteration for one problem, from the merged

@@ -183,15 +183,18 @@ class OracleRun:
         lib().orc_merge(self.n_chains, self.n_bins, self.hist, H)
         return H
 
-    def iterate(self, n_sweeps: int, ratio: float = 0.5, rule: int = 0):
+    def iterate(self, n_sweeps: int, ratio: float = 0.5, rule: int = 0, correct: bool = False):
         """One weight iteration: sweeps with histograms, merge, flatness on
-        the merged histogram, recursion, new table, cleared histograms."""
+        the merged histogram, recursion (optionally followed by the
+        correction function), new table, cleared histograms."""
         self.hist[:] = 0
         self.sweeps(n_sweeps, REC_MUCA)
         H = self.merged()
         fl = flatness(H, self.mask, ratio, rule)
         per_chain = self.hist.copy()
         lib().orc_recursion(self.n_bins, H, self.lnW)
+        if correct:
+            correction(self.lnW, H, self.mask, self.L)
         self.T = build_table(self.lnW)
         self.hist[:] = 0
         return H, fl, per_chain
@@ -204,6 +207,44 @@ class OracleRun:
         cnt = self.hist.astype(np.int64).sum(axis=0)
         sab = self.sabs.sum(axis=0)
         return cnt, sab
+
+
+# ------------------------------------------------------------------ correction
+
+def correction(lnW: np.ndarray, H: np.ndarray, mask: np.ndarray, L: int) -> None:
+    """The correction function of Sec. 3, in place: outside the sampled
+    region [lo, hi] (bins with H > 0) the log-weights continue on the straight
+    line through the edge bin and the bin L reachable bins inward (or the far
+    edge when the region is narrower)."""
+    nz = np.nonzero(H > 0)[0]
+    if nz.size == 0:
+        return
+    lo, hi = int(nz[0]), int(nz[-1])
+    if lo == hi:
+        return
+
+    def inward(edge, step):
+        k, count = edge, 0
+        while count < L:
+            nk = k + step
+            if nk < lo or nk > hi:
+                break
+            k = nk
+            if mask[k]:
+                count += 1
+        return k
+
+    a, b = inward(lo, 1), inward(hi, -1)
+    if a != lo:
+        slope = (lnW[lo] - lnW[a]) / float(lo - a)
+        for k in range(0, lo):
+            if mask[k]:
+                lnW[k] = lnW[lo] + slope * float(k - lo)
+    if b != hi:
+        slope = (lnW[hi] - lnW[b]) / float(hi - b)
+        for k in range(hi + 1, lnW.size):
+            if mask[k]:
+                lnW[k] = lnW[hi] + slope * float(k - hi)
 
 
 # ------------------------------------------------------------------ reweighting

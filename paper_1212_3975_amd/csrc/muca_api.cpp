@@ -153,6 +153,7 @@ muca_status validate(const muca_problem *pr, int32_t n, const muca_options *o) {
         if (o->spin_placement < 0 || o->spin_placement > 2 || o->table_placement < 0 || o->table_placement > 2)
             return fail(nullptr, MUCA_EINVAL, "placements must be 0..2");
         if (o->flat_rule < 0 || o->flat_rule > 1) return fail(nullptr, MUCA_EINVAL, "flat_rule must be 0 or 1");
+        if (o->correction < 0 || o->correction > 1) return fail(nullptr, MUCA_EINVAL, "correction must be 0 or 1");
     }
     return MUCA_OK;
 }
@@ -264,6 +265,41 @@ void stats_of(const ProbHost &p, const int64_t *H, double ratio, int rule, muca_
 void recursion(ProbHost &p, const int64_t *H) {
     for (int k = 0; k < p.nbins; ++k)
         if (H[k] > 0) p.lnW[k] -= std::log((double)H[k]);
+}
+
+// Correction function (Sec. 3): beyond each edge of the sampled region,
+// continue lnW on a straight line through the edge bin and the reachable bin
+// L reachable bins inward (or the other edge when the region is narrower).
+void correction(ProbHost &p, const int64_t *H) {
+    int lo = -1, hi = -1;
+    for (int k = 0; k < p.nbins; ++k)
+        if (H[k] > 0) {
+            if (lo < 0) lo = k;
+            hi = k;
+        }
+    if (lo < 0 || lo == hi) return;
+    const int L = p.def.L;
+    auto inward = [&](int edge, int dir) {
+        int k = edge, count = 0;
+        while (count < L) {
+            const int nk = k + dir;
+            if (nk < lo || nk > hi) break;
+            k = nk;
+            if (p.reach[k]) ++count;
+        }
+        return k;
+    };
+    const int in_lo = inward(lo, +1), in_hi = inward(hi, -1);
+    if (in_lo != lo) {
+        const double slope = (p.lnW[lo] - p.lnW[in_lo]) / (double)(lo - in_lo);
+        for (int k = 0; k < lo; ++k)
+            if (p.reach[k]) p.lnW[k] = p.lnW[lo] + slope * (double)(k - lo);
+    }
+    if (in_hi != hi) {
+        const double slope = (p.lnW[hi] - p.lnW[in_hi]) / (double)(hi - in_hi);
+        for (int k = hi + 1; k < p.nbins; ++k)
+            if (p.reach[k]) p.lnW[k] = p.lnW[hi] + slope * (double)(k - hi);
+    }
 }
 
 // Device-layout table of one problem (see muca_device.h).
@@ -536,6 +572,7 @@ void host_update(muca_ctx ctx, int update) {
         stats_of(p, H, ctx->opt.flat_ratio, ctx->opt.flat_rule, p.last);
         if (update) {
             recursion(p, H);
+            if (ctx->opt.correction) correction(p, H);
             device_table(p, ctx->pin_tab + p.tab_stage_off);
         }
     }

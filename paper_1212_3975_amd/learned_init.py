@@ -103,10 +103,13 @@ def test(params_path: str, out_dir: str, sizes, chains: int, sweeps: int, cap_pl
                 label = f"{NAMES[model]}{L} seed={seed} {arm}"
                 print(label, flush=True)
                 t0 = time.time()
-                with pm.Muca([prob]) as ctx:
-                    if arm == "learned":
+                # arms: "plain" / "learned" start from lnW = 0 / the prediction; a
+                # "+corr" suffix turns on the correction function of the recursion
+                base, _, extra = arm.partition("+")
+                with pm.Muca([prob], correction=int(extra == "corr")) as ctx:
+                    if base == "learned":
                         mlp.set_log_weights(ctx, 0)
-                    cap = cap_learned if arm == "learned" else cap_plain
+                    cap = cap_learned if base == "learned" else cap_plain
                     n_flat, hist = iterate_to_flat(ctx, sweeps, cap, label, log_every=25, max_seconds=max_seconds)
                 iters = n_flat if n_flat else cap
                 rec = {"model": NAMES[model], "L": L, "seed": seed, "arm": arm, "chains": chains,

@@ -51,3 +51,38 @@ def test_first_iteration_sampled_chains(plan):
         assert st2["total"] == prob.n_chains * M
         assert np.array_equal(_recompute_k(ctx.spins(), prob.L), ctx.k())
         assert np.all(ctx.H()[~ctx.reachable()] == 0)
+
+
+def test_mixed_batch_one_launch_sampled_chains():
+    """The nine-problem batch in one tuned launch (Ising L = 16..64 and
+    8-Potts L = 8..32, 512 chains each): per problem, eight chains recomputed
+    by the oracle match bit for bit after one iteration of 2000 sweeps, and
+    every chain keeps its invariants."""
+    import paper_1212_3975_amd as pm
+    from workloads import C4
+    probs = list(C4.problems)
+    M = C4.sweeps_per_iter
+    with pm.Muca(probs, use_graph=1) as ctx:
+        infos = [ctx.launch_info(i) for i in range(len(probs))]
+        print("launch", infos, flush=True)
+        ctx.sweep(M, pm.REC_MUCA)
+        for j, prob in enumerate(probs):
+            print(f"  problem {j}: model {prob.model} L {prob.L}", flush=True)
+            ch = ctx.chain_hist(j)
+            spins = ctx.spins(j)
+            k = ctx.k(j)
+            for c0 in (0, prob.n_chains - 4):
+                orc = oracle.OracleRun(prob.model, prob.L, 4, prob.seed, q=prob.q, chain0=c0)
+                orc.sweeps(M, oracle.REC_MUCA)
+                assert np.array_equal(ch[c0:c0 + 4], orc.hist)
+                assert np.array_equal(spins[c0:c0 + 4], orc.spins)
+                assert np.array_equal(k[c0:c0 + 4], orc.k)
+            assert np.array_equal(_recompute_k(spins, prob.L), k)
+        st = ctx.merge_update(True)
+        for j, prob in enumerate(probs):
+            assert st[j]["total"] == prob.n_chains * M
+        # the graph path continues from here with the same invariants
+        st = ctx.iterate(M)
+        for j, prob in enumerate(probs):
+            assert st[j]["total"] == prob.n_chains * M
+            assert np.array_equal(_recompute_k(ctx.spins(j), prob.L), ctx.k(j))

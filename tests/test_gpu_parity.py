@@ -229,3 +229,18 @@ def test_errors_are_reported():
             ctx.reweight(0, [0.4])
         with pytest.raises(pm.MucaError):
             ctx.set_log_weights(0, np.full(129, np.nan))
+
+
+@pytest.mark.parametrize("prob", [Problem(ISING, 16, 48, 51), Problem(POTTS, 8, 40, 52, q=8)],
+                         ids=["ising16", "potts8"])
+def test_correction_function_bit_exact(prob):
+    pm = _pm()
+    with pm.Muca([prob], correction=1) as ctx:
+        orc = _orc(prob)
+        for it in range(6):
+            print(f"  iteration {it}", flush=True)
+            st = ctx.iterate(150)[0]
+            H, fl, _ = orc.iterate(150, correct=True)
+            assert np.array_equal(ctx.H(), H)
+            assert _same_bits(ctx.lnW(), orc.lnW), f"lnW differs at iteration {it}"
+            assert np.array_equal(ctx.spins(), orc.spins)

@@ -267,3 +267,35 @@ def test_small_ising_run_reaches_exact_dos_L8():
     d = (-r.lnW - lo)[r.mask]
     d -= d.mean()
     assert np.abs(d).max() < 0.35 and d.std() < 0.1
+
+
+def test_correction_function_properties():
+    """The correction function (Sec. 3) leaves the sampled region alone, puts
+    every reachable bin outside it on the line through the edge bin and the
+    bin L reachable bins inward, and is the identity on weights that are
+    already linear in k."""
+    L = 6
+    mask = oracle.reachable(ISING, 2, L)
+    n = mask.size
+    H = np.zeros(n, np.int64)
+    H[20:41:2] = 5                      # sampled region k = 20..40
+    rng = np.random.default_rng(2)
+    lnW = rng.normal(0, 3, n)
+    before = lnW.copy()
+    oracle.correction(lnW, H, mask, L)
+    assert np.array_equal(lnW[20:41], before[20:41])
+    # lower edge: anchor 20 and the bin 6 reachable bins inward, k = 32
+    s = (before[20] - before[32]) / (20 - 32)
+    for k in range(0, 20):
+        if mask[k]:
+            assert lnW[k] == pytest.approx(before[20] + s * (k - 20), abs=1e-12)
+        else:
+            assert lnW[k] == before[k]
+    s = (before[40] - before[28]) / (40 - 28)
+    for k in range(41, n):
+        if mask[k]:
+            assert lnW[k] == pytest.approx(before[40] + s * (k - 40), abs=1e-12)
+    lin = 0.37 * np.arange(n) - 4.0
+    lin2 = lin.copy()
+    oracle.correction(lin2, H, mask, L)
+    assert np.allclose(lin2, lin, atol=1e-12)
