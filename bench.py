@@ -72,6 +72,31 @@ def cpu_baseline(prob, sweeps: int, n_chains: int):
                       f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
 
 
+def scan_chains(L, pm, torch, Problem, ISING):
+    """Sweep-kernel throughput of Ising L x L versus the number of chains (tuned
+    launch per count): the walkers are serial per chain, so throughput grows
+    with the chain count until the chip's LDS holds no more walkers."""
+    rows = []
+    for chains in (1024, 2048, 4096, 8192, 16384, 32768, 65536):
+        prob = Problem(ISING, L, chains, 7)
+        ctx = pm.Muca([prob], device="cuda:0", production=0)
+        sweeps = max(20, int(4e9 / (chains * L * L)))
+        ctx.sweep(sweeps, pm.REC_NONE)   # warm-up
+        ctx.sweep_timing()
+        ctx.sweep(sweeps, pm.REC_NONE)
+        ms, _ = ctx.sweep_timing()
+        rate = chains * L * L * sweeps / (ms * 1e-3)
+        info = ctx.launch_info()
+        ctx.close()
+        rows.append({"chains": chains, "sweeps": sweeps, "kernel_ms": round(ms, 3), "Gups": round(rate / 1e9, 2),
+                     "alu_frac": round(OPS_PER_ISING_UPDATE * rate / PEAK_INT32_OPS, 4),
+                     "chains_per_wg": info["chains_per_wg"], "fast_walker": info["fast_walker"],
+                     "workgroups": info["n_workgroups"]})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "sweep-kernel spin-update attempts/s vs chains", "unit": "G/s",
+                      "workload": f"2D Ising L={L}", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +110,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the production and reweighting leg")
     ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed"])
     ap.add_argument("--graph", action="store_true", help="run each iteration as one HIP graph launch")
+    ap.add_argument("--scan-chains", type=int, default=0, metavar="L",
+                    help="instead of the benchmark: sweep throughput of Ising L x L versus the number of chains")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size kernel for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -96,7 +123,11 @@ def main():
 
     import torch
     import paper_1212_3975_amd as pm
-    from workloads import C2, C3, C4
+    from workloads import C2, C3, C4, ISING, Problem
+
+    if args.scan_chains:
+        scan_chains(args.scan_chains, pm, torch, Problem, ISING)
+        return
 
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
