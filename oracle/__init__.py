@@ -8,7 +8,9 @@ The sampler, table and recursion are plain C loops (``muca_oracle.c``); this
 module wraps them with ctypes and adds, in plain numpy:
   - the flatness test of the weight iteration (Sec. 3: full range covered and
     every entry within bounds of the others);
-  - time-series reweighting, Eq. (2), written over energy bins.
+  - time-series reweighting, Eq. (2), written over energy bins;
+  - the interface tension of Eq. (9) from the equal-height reweighted
+    energy histogram (Sec. 5).
 """
 import ctypes
 import os
@@ -277,3 +279,62 @@ def reweight(model: int, L: int, lnW: np.ndarray, cnt: np.ndarray, sabs: np.ndar
         c_out.append(beta * beta * var / N)
         m_out.append(am / N)
     return np.array(e_out), np.array(c_out), np.array(m_out)
+
+
+# ------------------------------------------------------------------ interface tension
+
+def _log_canonical(model: int, L: int, lnW: np.ndarray, cnt: np.ndarray, beta: float):
+    """Bins with data and their log canonical probability, up to a constant:
+    a measurement in bin k carries exp(-beta E_k) / W(E_k) (Eq. 2), so
+    ln P_beta(k) = ln cnt_k - lnW_k - beta E_k."""
+    E = energies(model, L)
+    ks = np.flatnonzero(np.asarray(cnt) > 0)
+    a = np.log(np.asarray(cnt, np.float64)[ks]) - np.asarray(lnW, np.float64)[ks] - beta * E[ks]
+    return ks, a
+
+
+def _two_peaks(model, L, lnW, cnt, beta):
+    """The ordered and disordered peaks and the minimum between them.
+
+    Reading: the two peaks are the largest ln P on either side of the mean bin
+    (weights P), the minimum the smallest ln P between the two peaks."""
+    ks, a = _log_canonical(model, L, lnW, cnt, beta)
+    p = np.exp(a - a.max())
+    split = int(np.floor((p * ks).sum() / p.sum()))
+    low, high = ks <= split, ks > split
+    if not low.any() or not high.any():
+        raise ValueError("no two peaks")
+    i_o = np.flatnonzero(low)[np.argmax(a[low])]
+    i_d = np.flatnonzero(high)[np.argmax(a[high])]
+    i_m = i_o + int(np.argmin(a[i_o:i_d + 1]))
+    return (int(ks[i_o]), int(ks[i_m]), int(ks[i_d])), (a[i_o], a[i_m], a[i_d])
+
+
+def interface_tension(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: float):
+    """Order-disorder interface tension, Eq. (9), Sec. 5.
+
+    Step 1: find the inverse temperature at which the histogram reweighted to
+    the canonical ensemble has two equally high peaks (bisection on the
+    difference of the two log peak heights, which grows with beta because the
+    ordered peak has the lower energy).  Step 2: sigma_od = ln(P_max/P_min) /
+    (2L) there, with P_max the common peak height.  Returns (beta, sigma,
+    (k_ordered, k_min, k_disordered))."""
+    def gap(beta):
+        _, (ao, _, ad) = _two_peaks(model, L, lnW, cnt, beta)
+        return ao - ad
+    lo, hi = float(beta_lo), float(beta_hi)
+    if not (gap(lo) < 0.0 < gap(hi)):
+        raise ValueError("peak heights do not cross in the bracket")
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if not (lo < mid < hi):
+            break
+        if gap(mid) < 0.0:
+            lo = mid
+        else:
+            hi = mid
+    beta = 0.5 * (lo + hi)
+    ks, (ao, am, ad) = _two_peaks(model, L, lnW, cnt, beta)
+    if not ks[0] < ks[1] < ks[2]:
+        raise ValueError("no minimum between the peaks: one peak only")
+    return beta, (0.5 * (ao + ad) - am) / (2.0 * L), ks

@@ -1,0 +1,104 @@
+"""Pins of the oracle's interface-tension analysis (Sec. 5, Eq. 9).
+
+The pin is a closed form.  Take a density of states ln Omega(E) = b* E + f(k)
+with f(k) = h cos(2 pi (k - k1) / P) on a window of bins symmetric about
+k1 + P/2, and give every bin the same count with lnW = -ln Omega (a flat
+multicanonical histogram).  The reweighted log-probability at beta is then
+f(k) + (b* - beta) E_k.  At beta = b*, it has two equal peaks of height h, at
+k1 and k1 + P, and the minimum -h halfway between them.  So the equal-height
+beta is b*, and sigma_od = (h - (-h)) / (2L) = h / L.  A wrong sign of
+beta E, a dropped ln cnt, a wrong factor in 1/(2L) or an unequal-height beta
+each move one of these values.  The bracket of beta is kept narrow enough that
+the tilt (beta - b*) E across the two peaks stays below the barrier 2h; wider,
+the tilt piles the probability onto the edges of the window and makes new
+crossings, which a real multicanonical histogram (covering every bin) does not
+have.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ISING, POTTS
+
+B0_POTTS8 = math.log(1.0 + math.sqrt(8.0))   # Sec. 3: first-order transition of the 8-state Potts model
+
+
+def double_well(model, L, k1, period, h, beta_star, counts=None):
+    N = L * L
+    nb = 2 * N + 1
+    E = oracle.energies(model, L)
+    k = np.arange(nb)
+    lo, hi = k1 - period // 2 + 1, k1 + period + period // 2 - 1
+    ln_omega = beta_star * E + h * np.cos(2.0 * np.pi * (k - k1) / period)
+    cnt = np.zeros(nb, np.int64)
+    cnt[lo:hi + 1] = 1 if counts is None else counts[lo:hi + 1]
+    lnW = -ln_omega + np.log(np.maximum(cnt, 1))   # flat in the recorded counts' units
+    return lnW, cnt
+
+
+@pytest.mark.parametrize("model,L,k1,period", [(POTTS, 8, 30, 40), (POTTS, 12, 60, 80), (ISING, 8, 20, 30)])
+@pytest.mark.parametrize("tilt", [0.0, 0.037, -0.11])
+def test_equal_height_closed_form(model, L, k1, period, tilt):
+    h = 1.7
+    beta_star = B0_POTTS8 + tilt
+    lnW, cnt = double_well(model, L, k1, period, h, beta_star)
+    beta, sigma, ks = oracle.interface_tension(model, L, lnW, cnt, beta_star - 0.04, beta_star + 0.03)
+    assert beta == pytest.approx(beta_star, abs=1e-12)
+    assert sigma == pytest.approx(h / L, rel=1e-12)
+    assert ks == (k1, k1 + period // 2, k1 + period)
+
+
+def test_equal_height_uses_the_counts():
+    # uneven counts with lnW carrying the same factor describe the same ensemble
+    rng = np.random.default_rng(5)
+    L, k1, period = 8, 30, 40
+    counts = rng.integers(50, 5000, size=2 * L * L + 1)
+    lnW, cnt = double_well(POTTS, L, k1, period, 1.3, B0_POTTS8, counts)
+    beta, sigma, ks = oracle.interface_tension(POTTS, L, lnW, cnt, B0_POTTS8 - 0.04, B0_POTTS8 + 0.03)
+    assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
+    assert sigma == pytest.approx(1.3 / L, rel=1e-12)
+    # the same weights read with unit counts (ln cnt dropped, a plausible slip)
+    # describe another ensemble and give another answer
+    try:
+        b2, s2, _ = oracle.interface_tension(POTTS, L, lnW, np.where(cnt > 0, 1, 0), B0_POTTS8 - 0.04,
+                                             B0_POTTS8 + 0.03)
+    except ValueError:   # no crossing in the bracket at all
+        return
+    assert abs(b2 - beta) > 1e-6 or abs(s2 - sigma) > 1e-6
+
+
+def test_equal_height_with_a_long_disordered_tail():
+    # Potts-like asymmetry: a long declining tail on the high-energy side puts
+    # the middle of the sampled range beyond both peaks; the split at the mean
+    # of the reweighted distribution still falls between them
+    L, k1, period, h, tail = 12, 60, 80, 1.9, 100
+    N = L * L
+    E = oracle.energies(POTTS, L)
+    k = np.arange(2 * N + 1)
+    lo, hi = k1 - period // 2 + 1, k1 + period + period // 2 - 1
+    f = h * np.cos(2.0 * np.pi * (k - k1) / period)
+    f = np.where(k > hi, f[hi] - 0.05 * (k - hi), f)
+    cnt = np.zeros(2 * N + 1, np.int64)
+    cnt[lo:hi + tail + 1] = 1
+    assert (lo + hi + tail) // 2 > k1 + period
+    lnW = -(B0_POTTS8 * E + f)
+    beta, sigma, ks = oracle.interface_tension(POTTS, L, lnW, cnt, B0_POTTS8 - 0.02, B0_POTTS8 + 0.015)
+    assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
+    assert sigma == pytest.approx(h / L, rel=1e-12)
+    assert ks == (k1, k1 + period // 2, k1 + period)
+
+
+def test_equal_height_refuses_one_peak_and_a_bad_bracket():
+    L = 8
+    N = L * L
+    E = oracle.energies(POTTS, L)
+    k = np.arange(2 * N + 1)
+    ln_omega = B0_POTTS8 * E - 0.01 * (k - 60.0) ** 2   # one peak
+    cnt = np.ones(2 * N + 1, np.int64)
+    with pytest.raises(ValueError):
+        oracle.interface_tension(POTTS, L, -ln_omega, cnt, B0_POTTS8 - 0.2, B0_POTTS8 + 0.2)
+    lnW, cnt = double_well(POTTS, L, 30, 40, 1.0, B0_POTTS8)
+    with pytest.raises(ValueError):   # both ends above the equal-height beta
+        oracle.interface_tension(POTTS, L, lnW, cnt, B0_POTTS8 + 0.05, B0_POTTS8 + 0.2)
