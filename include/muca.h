@@ -170,6 +170,42 @@ muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_
 /* Zeroes the per-chain production accumulators of every problem. */
 muca_status mucaClearProduction(muca_ctx ctx);
 
+/* Order-disorder interface tension from a reweighted energy histogram
+ * (Sec. 5, Eq. 9): find the inverse temperature beta_eqh at which the
+ * histogram reweighted to the canonical ensemble shows two equally high
+ * peaks, and return sigma_od = ln(P_max / P_min) / (2L) there.
+ *
+ * At beta, bin k with cnt[k] > 0 carries a_k = ln cnt[k] - lnW[k] - beta E_k
+ * (E_k as in the conventions above; the log of the canonical probability up
+ * to a constant; bins with cnt[k] = 0 are left out).  Peaks: the maxima of a
+ * over k <= floor(kbar) (ordered) and over k > floor(kbar) (disordered), kbar
+ * being the bin index averaged with weights e^{a_k}; minimum: the smallest a_k
+ * between the two peaks (first index on ties).  beta_eqh is found by
+ * bisection of a(ordered peak) - a(disordered peak), which must be < 0 at
+ * beta_lo and > 0 at beta_hi; ln(P_max/P_min) uses the mean of the two peak
+ * heights.  Host computation in IEEE double with the C library's log/exp.
+ *
+ *   model, L     MUCA_ISING or MUCA_POTTS and the lattice side; n_bins = 2N+1
+ *   lnW, cnt     host arrays of n_bins (log-weights of the production run and
+ *                its merged counts), caller-owned
+ *   beta_eqh, sigma_od  outputs
+ *   k_peaks      int32[3] or NULL: ordered peak, minimum, disordered peak bins
+ *   lnP          double[n_bins] or NULL: the normalised log-probabilities at
+ *                beta_eqh (-HUGE_VAL where cnt = 0)
+ * Returns MUCA_EINVAL for bad arguments and MUCA_ESTATE when the histogram has
+ * no two peaks (at beta_eqh no bin lies strictly between them) or their
+ * heights do not cross inside [beta_lo, beta_hi].
+ * Needs no GPU and no context (errors: mucaLastError(NULL)). */
+muca_status mucaEqualHeight(int32_t model, int32_t L, const double *lnW, const int64_t *cnt, int32_t n_bins,
+                            double beta_lo, double beta_hi, double *beta_eqh, double *sigma_od, int32_t *k_peaks,
+                            double *lnP);
+
+/* mucaEqualHeight applied to problem prob's production data (merged counts of
+ * the MUCA_REC_PROD sweeps since the last mucaClearProduction) and its current
+ * log-weights.  MUCA_ESTATE without production data.  Synchronises. */
+muca_status mucaInterfaceTension(muca_ctx ctx, int32_t prob, double beta_lo, double beta_hi, double *beta_eqh,
+                                 double *sigma_od, int32_t *k_peaks, double *lnP);
+
 /* Copies state of problem prob to host memory (bytes must match exactly):
  *   MUCA_GET_H        int64[2N+1]      merged histogram of the last merge
  *   MUCA_GET_LNW      double[2N+1]     current log-weights

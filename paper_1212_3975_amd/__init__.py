@@ -21,6 +21,7 @@ GET_H, GET_LNW, GET_T, GET_SPINS, GET_K, GET_M, GET_CHAIN_H, GET_PROD_CNT, GET_P
 EXPORTED = ["mucaWorkspaceSize", "mucaInit", "mucaSetLogWeights", "mucaSweep", "mucaMergeUpdate",
             "mucaIterate", "mucaReweight", "mucaClearProduction", "mucaGet", "mucaLaunchInfo",
             "mucaSweepTiming", "mucaCheckpoint", "mucaRestore", "mucaProblemInfo", "mucaDestroy", "mucaLastError",
+            "mucaEqualHeight", "mucaInterfaceTension",
             "mucaMlpWorkspaceSize", "mucaMlpCreate", "mucaMlpSetParams", "mucaMlpGetParams", "mucaMlpClearData",
             "mucaMlpAddData", "mucaMlpAddWeights", "mucaMlpNumSamples", "mucaMlpTrain", "mucaMlpGradients",
             "mucaMlpPredict", "mucaMlpSetLogWeights", "mucaMlpDestroy", "mucaMlpLastError"]
@@ -98,6 +99,11 @@ def lib():
         L.mucaDestroy.restype = None
         L.mucaLastError.argtypes = [vp]
         L.mucaLastError.restype = ctypes.c_char_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(i32)
+        L.mucaEqualHeight.argtypes = [i32, i32, dp, ctypes.POINTER(ctypes.c_int64), i32, ctypes.c_double,
+                                      ctypes.c_double, dp, dp, ip, dp]
+        L.mucaInterfaceTension.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double, dp, dp, ip, dp]
         fp = ctypes.POINTER(ctypes.c_float)
         L.mucaMlpWorkspaceSize.argtypes = [i32, ctypes.POINTER(sz)]
         L.mucaMlpCreate.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64, vp, sz, vp]
@@ -216,6 +222,16 @@ class Muca:
                                    _dptr(m, ctypes.c_double)))
         return e, c, m
 
+    def interface_tension(self, prob: int, beta_lo: float, beta_hi: float):
+        """Equal-height inverse temperature and sigma_od = ln(P_max/P_min)/(2L)
+        of problem prob's production data (Sec. 5, Eq. 9)."""
+        beta, sigma = ctypes.c_double(), ctypes.c_double()
+        k3 = (ctypes.c_int32 * 3)()
+        lnP = np.zeros(self._dims(prob)[1])
+        self._c(lib().mucaInterfaceTension(self._ctx, prob, float(beta_lo), float(beta_hi), ctypes.byref(beta),
+                                           ctypes.byref(sigma), k3, _dptr(lnP, ctypes.c_double)))
+        return {"beta": beta.value, "sigma": sigma.value, "k_peaks": tuple(k3), "lnP": lnP}
+
     # -- state
     def _get(self, what: int, prob: int, dtype, shape):
         out = np.zeros(shape, dtype)
@@ -297,6 +313,24 @@ def _f32(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def equal_height(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: float):
+    """mucaEqualHeight on host arrays (no GPU needed): the equal-height inverse
+    temperature of the reweighted energy histogram and sigma_od (Sec. 5, Eq. 9)."""
+    w = np.ascontiguousarray(lnW, np.float64)
+    c = np.ascontiguousarray(cnt, np.int64)
+    if w.shape != c.shape:
+        raise ValueError("lnW and cnt differ in size")
+    beta, sigma = ctypes.c_double(), ctypes.c_double()
+    k3 = (ctypes.c_int32 * 3)()
+    lnP = np.zeros(w.size)
+    rc = lib().mucaEqualHeight(int(model), int(L), _dptr(w, ctypes.c_double),
+                               c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), w.size, float(beta_lo),
+                               float(beta_hi), ctypes.byref(beta), ctypes.byref(sigma), k3,
+                               _dptr(lnP, ctypes.c_double))
+    _check(rc)
+    return {"beta": beta.value, "sigma": sigma.value, "k_peaks": tuple(k3), "lnP": lnP}
 
 
 class Mlp:

@@ -591,6 +591,95 @@ muca_status check_prob(muca_ctx ctx, int32_t prob) {
     return MUCA_OK;
 }
 
+// Equal-height analysis of a reweighted energy histogram (Sec. 5, Eq. 9).
+// At inverse temperature beta, bin k with cnt_k > 0 carries
+// a_k = ln cnt_k - lnW_k - beta E_k (the log of the canonical probability up to
+// a constant).  The two peaks are the maxima of a on either side of the
+// weighted mean bin; the minimum is taken between them.
+struct PeakSplit {
+    int ko = -1, km = -1, kd = -1;   // ordered peak, minimum, disordered peak
+    double ao = 0, am = 0, ad = 0;
+};
+
+bool split_peaks(const int64_t *cnt, const double *lnW, const double *E, int nb, double beta, PeakSplit &ps) {
+    std::vector<double> a(nb, 0.0);
+    double A = -HUGE_VAL;
+    for (int k = 0; k < nb; ++k)
+        if (cnt[k] > 0) {
+            a[k] = std::log((double)cnt[k]) - lnW[k] - beta * E[k];
+            if (a[k] > A) A = a[k];
+        }
+    if (A == -HUGE_VAL) return false;
+    double z = 0.0, zk = 0.0;
+    for (int k = 0; k < nb; ++k)
+        if (cnt[k] > 0) {
+            const double w = std::exp(a[k] - A);
+            z += w;
+            zk += w * (double)k;
+        }
+    const int split = (int)std::floor(zk / z);
+    ps = PeakSplit();
+    for (int k = 0; k < nb; ++k) {
+        if (cnt[k] <= 0) continue;
+        if (k <= split) {
+            if (ps.ko < 0 || a[k] > ps.ao) ps.ko = k, ps.ao = a[k];
+        } else {
+            if (ps.kd < 0 || a[k] > ps.ad) ps.kd = k, ps.ad = a[k];
+        }
+    }
+    if (ps.ko < 0 || ps.kd < 0) return false;
+    for (int k = ps.ko; k <= ps.kd; ++k)
+        if (cnt[k] > 0 && (ps.km < 0 || a[k] < ps.am)) ps.km = k, ps.am = a[k];
+    return true;
+}
+
+muca_status equal_height(muca_ctx ctx, int32_t model, int32_t L, const double *lnW, const int64_t *cnt,
+                         int32_t n_bins, double beta_lo, double beta_hi, double *beta_out, double *sigma_out,
+                         int32_t *k3, double *lnP) {
+    if ((model != MUCA_ISING && model != MUCA_POTTS) || L < 2 || !lnW || !cnt || !beta_out || !sigma_out)
+        return fail(ctx, MUCA_EINVAL, "bad arguments");
+    const int N = L * L, nb = 2 * N + 1;
+    if (n_bins != nb) return fail(ctx, MUCA_EINVAL, "n_bins must be 2N+1 = %d", nb);
+    if (!(beta_lo < beta_hi)) return fail(ctx, MUCA_EINVAL, "need beta_lo < beta_hi");
+    std::vector<double> E(nb);
+    for (int k = 0; k < nb; ++k) E[k] = (double)(-2 * N + (model == MUCA_ISING ? 2 * k : k));
+    PeakSplit lo_ps, hi_ps;
+    if (!split_peaks(cnt, lnW, E.data(), nb, beta_lo, lo_ps) || !split_peaks(cnt, lnW, E.data(), nb, beta_hi, hi_ps))
+        return fail(ctx, MUCA_ESTATE, "histogram has no two peaks");
+    // the ordered (low-energy) peak gains on the disordered one as beta grows
+    if (!(lo_ps.ao - lo_ps.ad < 0.0 && hi_ps.ao - hi_ps.ad > 0.0))
+        return fail(ctx, MUCA_ESTATE, "peak heights do not cross in [%g, %g]", beta_lo, beta_hi);
+    double lo = beta_lo, hi = beta_hi;
+    PeakSplit ps;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (!split_peaks(cnt, lnW, E.data(), nb, mid, ps)) return fail(ctx, MUCA_ESTATE, "lost the two peaks");
+        if (ps.ao - ps.ad < 0.0) lo = mid;
+        else hi = mid;
+    }
+    const double beta = 0.5 * (lo + hi);
+    if (!split_peaks(cnt, lnW, E.data(), nb, beta, ps)) return fail(ctx, MUCA_ESTATE, "lost the two peaks");
+    // a single peak splits into two neighbouring "maxima" with no bin between them
+    if (!(ps.ko < ps.km && ps.km < ps.kd)) return fail(ctx, MUCA_ESTATE, "histogram has no two peaks");
+    *beta_out = beta;
+    *sigma_out = (0.5 * (ps.ao + ps.ad) - ps.am) / (2.0 * L);
+    if (k3) k3[0] = ps.ko, k3[1] = ps.km, k3[2] = ps.kd;
+    if (lnP) {
+        // normalised log-probabilities at the equal-height beta, -inf where cnt = 0
+        double A = -HUGE_VAL;
+        for (int k = 0; k < nb; ++k)
+            if (cnt[k] > 0) A = std::max(A, std::log((double)cnt[k]) - lnW[k] - beta * E[k]);
+        double z = 0.0;
+        for (int k = 0; k < nb; ++k)
+            if (cnt[k] > 0) z += std::exp(std::log((double)cnt[k]) - lnW[k] - beta * E[k] - A);
+        const double lz = A + std::log(z);
+        for (int k = 0; k < nb; ++k)
+            lnP[k] = (cnt[k] > 0) ? std::log((double)cnt[k]) - lnW[k] - beta * E[k] - lz : -HUGE_VAL;
+    }
+    return MUCA_OK;
+}
+
 void drop_graph(muca_ctx ctx) {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -840,6 +929,28 @@ muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_
     std::memcpy(c_v, res.data() + n_betas, 8 * n_betas);
     std::memcpy(abs_m_per_site, res.data() + 2 * n_betas, 8 * n_betas);
     return MUCA_OK;
+}
+
+muca_status mucaEqualHeight(int32_t model, int32_t L, const double *lnW, const int64_t *cnt, int32_t n_bins,
+                            double beta_lo, double beta_hi, double *beta_eqh, double *sigma_od, int32_t *k_peaks,
+                            double *lnP) {
+    return equal_height(nullptr, model, L, lnW, cnt, n_bins, beta_lo, beta_hi, beta_eqh, sigma_od, k_peaks, lnP);
+}
+
+muca_status mucaInterfaceTension(muca_ctx ctx, int32_t prob, double beta_lo, double beta_hi, double *beta_eqh,
+                                 double *sigma_od, int32_t *k_peaks, double *lnP) {
+    muca_status st = check_prob(ctx, prob);
+    if (st) return st;
+    ProbHost &p = ctx->probs[prob];
+    if (!p.prod_data) return fail(ctx, MUCA_ESTATE, "no production data");
+    // merge the production accumulators (counts into H), keep them
+    HIPCHECK(ctx, launch_merge(ctx->d_probs, ctx->d_merge, (int)ctx->merge_items.size(), 1, 0, ctx->stream));
+    std::vector<int64_t> cnt(p.nbins);
+    HIPCHECK(ctx, hipMemcpyAsync(cnt.data(), ctx->h_probdev[prob].H, 8 * (size_t)p.nbins, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return equal_height(ctx, p.def.model, p.def.L, p.lnW.data(), cnt.data(), p.nbins, beta_lo, beta_hi, beta_eqh,
+                        sigma_od, k_peaks, lnP);
 }
 
 muca_status mucaGet(muca_ctx ctx, int32_t what, int32_t prob, void *dst, size_t bytes) {
