@@ -244,3 +244,33 @@ def test_correction_function_bit_exact(prob):
             assert np.array_equal(ctx.H(), H)
             assert _same_bits(ctx.lnW(), orc.lnW), f"lnW differs at iteration {it}"
             assert np.array_equal(ctx.spins(), orc.spins)
+
+
+def test_interface_tension_of_a_production_run():
+    """8-state Potts L=16: weights iterated (with the correction function) to a
+    flat histogram, a production run, then the equal-height analysis (Sec. 5,
+    Eq. 9) of the library on its own production data against the oracle's on
+    the same counts and weights."""
+    import math
+    pm = _pm()
+    prob = Problem(POTTS, 16, 2048, 61, q=8)
+    b0 = math.log(1.0 + math.sqrt(8.0))
+    with pm.Muca([prob], correction=1) as ctx:
+        flat = False
+        for it in range(150):
+            if ctx.iterate(1000)[0]["flat"]:
+                flat = True
+                break
+        assert flat, "no flat histogram within 150 iterations"
+        ctx.sweep(1000, pm.REC_NONE)
+        ctx.sweep(4000, pm.REC_PROD)
+        got = ctx.interface_tension(0, b0 - 0.05, b0 + 0.05)
+        cnt, lnW = ctx.prod_counts(0), ctx.lnW(0)
+    assert cnt.sum() == 2048 * 4000
+    beta, sigma, ks = oracle.interface_tension(POTTS, 16, lnW, cnt, b0 - 0.05, b0 + 0.05)
+    print(f"  beta_eqh={got['beta']:.6f} sigma={got['sigma']:.5f} peaks={got['k_peaks']}", flush=True)
+    assert got["beta"] == pytest.approx(beta, rel=1e-12)
+    assert got["sigma"] == pytest.approx(sigma, rel=1e-10)
+    assert got["k_peaks"] == ks
+    # a first-order double peak: ordered peak at low k, disordered at high k
+    assert ks[0] < ks[1] < ks[2] and 0.0 < got["sigma"] < 0.2
