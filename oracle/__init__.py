@@ -21,9 +21,10 @@ import numpy as np
 
 from . import build as _build
 
-ISING, POTTS = 0, 1
+ISING, POTTS, ISING_MAG = 0, 1, 2
 REC_NONE, REC_MUCA, REC_PROD = 0, 1, 2
 TCOLS = 9
+TCOLS_MAG = 10
 
 _lib = None
 
@@ -47,12 +48,15 @@ def lib():
                                                ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]
         L.orc_init.argtypes = [c_int, c_int, c_int, c_int, c_int, c_u64, u8p, i32p, i32p]
         L.orc_build_table.argtypes = [c_int, f64p, u32p]
+        L.orc_build_table_mag.argtypes = [c_int, c_dbl, f64p, u32p]
+        L.orc_bruteforce_mag.argtypes = [c_int, c_dbl, f64p, f64p]
         L.orc_sweeps.argtypes = [c_int, c_int, c_int, c_int, c_int, c_u64, c_u32, c_int, c_int, u32p, u8p,
                                  i32p, i32p, i32p, i64p, c_int]
         L.orc_merge.argtypes = [c_int, c_int, i32p, i64p]
         L.orc_recursion.argtypes = [c_int, i64p, f64p]
         for f in ("orc_philox4x32_10", "orc_energy", "orc_reachable", "orc_bruteforce",
-                  "orc_bruteforce_canonical", "orc_init", "orc_build_table", "orc_sweeps",
+                  "orc_bruteforce_canonical", "orc_init", "orc_build_table", "orc_build_table_mag",
+                  "orc_bruteforce_mag", "orc_sweeps",
                   "orc_merge", "orc_recursion"):
             getattr(L, f).restype = None
         _lib = L
@@ -77,8 +81,14 @@ def energy(model: int, L: int, spins: np.ndarray):
     return k.value, m.value
 
 
+def n_bins_of(model: int, L: int) -> int:
+    """2N+1 energy bins (k = 0..2N), or N+1 magnetization bins (m = number of
+    up spins) for the multimagnetic ensemble."""
+    return L * L + 1 if model == ISING_MAG else 2 * L * L + 1
+
+
 def reachable(model: int, q: int, L: int) -> np.ndarray:
-    mask = np.zeros(2 * L * L + 1, np.uint8)
+    mask = np.zeros(n_bins_of(model, L), np.uint8)
     lib().orc_reachable(model, q, L, mask)
     return mask.astype(bool)
 
@@ -102,6 +112,24 @@ def build_table(lnW: np.ndarray) -> np.ndarray:
     T = np.zeros((lnW.size, TCOLS), np.uint32)
     lib().orc_build_table(lnW.size, lnW, T)
     return T
+
+
+def build_table_mag(L: int, beta: float, lnW: np.ndarray) -> np.ndarray:
+    """Multimagnetic thresholds [N+1][10]: row m (up spins), column j + 5u
+    (u = 1 for an up spin, flip changes k by 2j - 4 and m by -1 or +1)."""
+    lnW = np.ascontiguousarray(lnW, np.float64)
+    assert lnW.size == L * L + 1
+    T = np.zeros((lnW.size, TCOLS_MAG), np.uint32)
+    lib().orc_build_table_mag(L, float(beta), lnW, T)
+    return T
+
+
+def bruteforce_mag(L: int, beta: float):
+    """Exact canonical P(m) and the mean bond count k at each m, by
+    enumerating all 2^N Ising states (m = number of up spins)."""
+    p, km = np.zeros(L * L + 1), np.zeros(L * L + 1)
+    lib().orc_bruteforce_mag(L, float(beta), p, km)
+    return p, km
 
 
 def energies(model: int, L: int) -> np.ndarray:
@@ -151,12 +179,14 @@ class OracleRun:
     """One MUCA problem on the CPU: spins, per-chain state, lnW and T."""
 
     def __init__(self, model: int, L: int, n_chains: int, seed: int, q: int = 2,
-                 n_threads: Optional[int] = None, chain0: int = 0):
+                 n_threads: Optional[int] = None, chain0: int = 0, beta: float = 0.0):
         """Chains chain0 .. chain0 + n_chains - 1 of the problem (a chain's
-        trajectory depends only on the seed, its index and lnW)."""
+        trajectory depends only on the seed, its index and lnW).  beta: the
+        fixed inverse temperature of the multimagnetic ensemble (ISING_MAG)."""
         self.model, self.L, self.q, self.seed = model, L, q if model == POTTS else 2, seed
+        self.beta = float(beta)
         self.N = L * L
-        self.n_bins = 2 * self.N + 1
+        self.n_bins = n_bins_of(model, L)
         self.n_chains = n_chains
         self.chain0 = chain0
         self.n_threads = n_threads or default_threads()
@@ -165,15 +195,20 @@ class OracleRun:
         self.m = np.zeros(n_chains, np.int32)
         lib().orc_init(model, self.q, L, chain0, n_chains, seed, self.spins, self.k, self.m)
         self.lnW = np.zeros(self.n_bins, np.float64)
-        self.T = build_table(self.lnW)
+        self.T = self._table()
         self.hist = np.zeros((n_chains, self.n_bins), np.int32)
         self.sabs = np.zeros((n_chains, self.n_bins), np.int64)
         self.sweep = 0
         self.mask = reachable(model, self.q, L)
 
+    def _table(self) -> np.ndarray:
+        if self.model == ISING_MAG:
+            return build_table_mag(self.L, self.beta, self.lnW)
+        return build_table(self.lnW)
+
     def set_log_weights(self, lnW: np.ndarray):
         self.lnW = np.array(lnW, np.float64)
-        self.T = build_table(self.lnW)
+        self.T = self._table()
 
     def sweeps(self, n: int, record: int):
         lib().orc_sweeps(self.model, self.q, self.L, self.chain0, self.n_chains, self.seed, self.sweep, n, record,
@@ -197,7 +232,7 @@ class OracleRun:
         lib().orc_recursion(self.n_bins, H, self.lnW)
         if correct:
             correction(self.lnW, H, self.mask, self.L)
-        self.T = build_table(self.lnW)
+        self.T = self._table()
         self.hist[:] = 0
         return H, fl, per_chain
 

@@ -17,7 +17,10 @@
  *     version: H = sum_i H_i);
  *   - the recursion W <- W / H kept in logarithms (Sec. 2), applied only to
  *     bins with a non-zero histogram entry (Sec. 3);
- *   - production accumulators for time-series reweighting, Eq. (2).
+ *   - production accumulators for time-series reweighting, Eq. (2);
+ *   - the multimagnetic Ising ensemble of Sec. 4 (weights over the
+ *     magnetization at a fixed inverse temperature beta): the same sweeps
+ *     with acceptance min(1, exp(-beta dE) W(M') / W(M)).
  *
  * Conventions fixed where the paper is silent:
  *   - energies are binned by k, the number of unsatisfied bonds, 0..2N
@@ -38,11 +41,16 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { MODEL_ISING = 0, MODEL_POTTS = 1 };
+enum { MODEL_ISING = 0, MODEL_POTTS = 1, MODEL_ISING_MAG = 2 };
 enum { REC_NONE = 0, REC_MUCA = 1, REC_PROD = 2 };
 enum { STREAM_SWEEP = 0, STREAM_INIT = 1 };
 
 #define TCOLS 9 /* threshold-table columns: dk = -4..4, column dk + 4 */
+/* Multimagnetic table: row m = number of up spins (M = 2m - N), column
+ * j + 5u, where u = 1 if the spin to flip is up, j = 4 - (disagreeing
+ * neighbours), so that the flip changes k by dk = 2j - 4 and m by -1 (up) or
+ * +1 (down). */
+#define TCOLS_MAG 10
 
 /* ---------------------------------------------------------------------- */
 /* Philox4x32-10                                                            */
@@ -111,7 +119,7 @@ void orc_energy(int model, int L, const uint8_t *s, int32_t *k_out, int32_t *m_o
         neighbours(L, i, nb);
         if (s[i] != s[nb[0]]) ++k;
         if (s[i] != s[nb[2]]) ++k;
-        if (model == MODEL_ISING) m += ising_value(s[i]);
+        if (model != MODEL_POTTS) m += ising_value(s[i]);
     }
     *k_out = k;
     *m_out = m;
@@ -131,6 +139,11 @@ void orc_reachable(int model, int q, int L, uint8_t *mask)
 {
     int N = L * L;
     (void)q;
+    if (model == MODEL_ISING_MAG) {
+        /* bins m = 0..N: any number of up spins occurs */
+        for (int m = 0; m <= N; ++m) mask[m] = 1;
+        return;
+    }
     for (int k = 0; k <= 2 * N; ++k) {
         int r;
         if (model == MODEL_ISING)
@@ -204,6 +217,38 @@ void orc_bruteforce_canonical(int model, int q, int L, double beta,
     *absm_mean = sm / z;
 }
 
+/* Exact canonical distribution of the Ising magnetization at beta: for every
+ * m = number of up spins, p_m = sum over states with m up spins of
+ * exp(-beta E) / Z, and e_m = the mean of k over those states (weighted the
+ * same way).  By enumeration of all 2^N states. */
+void orc_bruteforce_mag(int L, double beta, double *p_m, double *k_mean)
+{
+    int N = L * L;
+    uint8_t s[64];
+    memset(s, 0, sizeof(s));
+    double e_ground = -2.0 * N, z = 0;
+    for (int b = 0; b <= N; ++b) { p_m[b] = 0; k_mean[b] = 0; }
+    for (;;) {
+        int32_t k, m;
+        orc_energy(MODEL_ISING, L, s, &k, &m);
+        double w = exp(-beta * ((-2.0 * N + 2.0 * k) - e_ground));
+        z += w;
+        p_m[(m + N) / 2] += w;
+        k_mean[(m + N) / 2] += w * (double)k;
+        int i = 0;
+        while (i < N) {
+            if (++s[i] < 2) break;
+            s[i] = 0;
+            ++i;
+        }
+        if (i == N) break;
+    }
+    for (int b = 0; b <= N; ++b) {
+        if (p_m[b] > 0) k_mean[b] /= p_m[b];
+        p_m[b] /= z;
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Initial state: infinite temperature                                     */
 /* ---------------------------------------------------------------------- */
@@ -221,7 +266,7 @@ void orc_init(int model, int q, int L, int chain0, int n_chains, uint64_t seed,
         for (int i = 0; i < N; ++i) {
             uint32_t blk[4];
             draw_block(seed, (uint32_t)i, 0u, (uint32_t)(chain0 + c), STREAM_INIT, blk);
-            if (model == MODEL_ISING)
+            if (model != MODEL_POTTS)
                 s[i] = (uint8_t)(blk[0] >> 31);
             else
                 s[i] = (uint8_t)(((uint64_t)blk[0] * (uint64_t)q) >> 32);
@@ -237,22 +282,41 @@ void orc_init(int model, int q, int L, int chain0, int n_chains, uint64_t seed,
 /* T[k][dk+4] = floor(2^32 * min(1, exp(lnW[k+dk] - lnW[k]))) for 0 <= k+dk <= 2N;
  * cells whose target lies outside the range are 0 (never used).  A value that
  * would reach 2^32 - 1 or more is stored as 0xFFFFFFFF, read as "always". */
+static uint32_t threshold_of(double delta)
+{
+    if (delta >= 0.0) return 0xFFFFFFFFu;
+    double x = ldexp(exp(delta), 32);
+    return (x >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)floor(x);
+}
+
 void orc_build_table(int n_bins, const double *lnW, uint32_t *T)
 {
     for (int k = 0; k < n_bins; ++k) {
         for (int dk = -4; dk <= 4; ++dk) {
             int t = k + dk;
             uint32_t v = 0;
-            if (t >= 0 && t < n_bins) {
-                double delta = lnW[t] - lnW[k];
-                if (delta >= 0.0) {
-                    v = 0xFFFFFFFFu;
-                } else {
-                    double x = ldexp(exp(delta), 32);
-                    v = (x >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)floor(x);
-                }
-            }
+            if (t >= 0 && t < n_bins) v = threshold_of(lnW[t] - lnW[k]);
             T[(size_t)k * TCOLS + (dk + 4)] = v;
+        }
+    }
+}
+
+/* Multimagnetic table (layout above): the move from m to m' = m -+ 1 that
+ * changes the energy by dE = 2 dk (E = -2N + 2k) is accepted with probability
+ * min(1, exp(-beta dE) W(m') / W(m)); in logarithms
+ * delta = (lnW[m'] - lnW[m]) - beta * dE.  Targets outside 0..N are 0. */
+void orc_build_table_mag(int L, double beta, const double *lnW, uint32_t *T)
+{
+    int N = L * L;
+    for (int m = 0; m <= N; ++m) {
+        for (int u = 0; u < 2; ++u) {
+            int t = u ? m - 1 : m + 1;
+            for (int j = 0; j < 5; ++j) {
+                int dk = 2 * j - 4;
+                uint32_t v = 0;
+                if (t >= 0 && t <= N) v = threshold_of((lnW[t] - lnW[m]) - beta * (double)(2 * dk));
+                T[(size_t)m * TCOLS_MAG + j + 5 * u] = v;
+            }
         }
     }
 }
@@ -290,7 +354,7 @@ static void sweep_one_chain(const sweep_job *j, int c, uint32_t sweep)
         int before = 0, after = 0;
         uint8_t s_new;
         uint32_t u;
-        if (j->model == MODEL_ISING) {
+        if (j->model != MODEL_POTTS) {
             /* four sites share one block: site i uses word i mod 4 */
             if ((i & 3) == 0) draw_block(j->seed, (uint32_t)(i >> 2), sweep, (uint32_t)(j->chain0 + c), STREAM_SWEEP, blk);
             u = blk[i & 3];
@@ -309,16 +373,29 @@ static void sweep_one_chain(const sweep_job *j, int c, uint32_t sweep)
             if (s[nb[n]] != s_new) ++after;
         }
         int dk = after - before;
-        uint32_t tv = j->T[(size_t)k * TCOLS + (dk + 4)];
+        uint32_t tv;
+        if (j->model == MODEL_ISING_MAG) {
+            /* row: up spins (m + N) / 2; column by dk and the spin's value */
+            tv = j->T[(size_t)((m + N) / 2) * TCOLS_MAG + (dk + 4) / 2 + (s[i] ? 5 : 0)];
+        } else {
+            tv = j->T[(size_t)k * TCOLS + (dk + 4)];
+        }
         if (accept(u, tv)) {
-            if (j->model == MODEL_ISING) m += ising_value(s_new) - ising_value(s[i]);
+            if (j->model != MODEL_POTTS) m += ising_value(s_new) - ising_value(s[i]);
             s[i] = s_new;
             k += dk;
         }
     }
     if (j->record != REC_NONE) {
-        j->hist[(size_t)c * j->n_bins + k] += 1;
-        if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + k] += (m < 0) ? -m : m;
+        if (j->model == MODEL_ISING_MAG) {
+            /* bin m (up spins); production adds the bond count k of the measurement */
+            int b = (m + N) / 2;
+            j->hist[(size_t)c * j->n_bins + b] += 1;
+            if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + b] += k;
+        } else {
+            j->hist[(size_t)c * j->n_bins + k] += 1;
+            if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + k] += (m < 0) ? -m : m;
+        }
     }
     j->k[c] = k;
     j->m[c] = m;
@@ -347,7 +424,8 @@ void orc_sweeps(int model, int q, int L, int chain0, int n_chains, uint64_t seed
     int per = n_chains / n_threads, rem = n_chains % n_threads, c0 = 0;
     for (int t = 0; t < n_threads; ++t) {
         sweep_job *j = &jobs[t];
-        j->model = model; j->q = q; j->L = L; j->n_bins = 2 * L * L + 1; j->chain0 = chain0;
+        j->model = model; j->q = q; j->L = L; j->chain0 = chain0;
+        j->n_bins = (model == MODEL_ISING_MAG) ? L * L + 1 : 2 * L * L + 1;
         j->c_begin = c0; j->c_end = c0 + per + (t < rem ? 1 : 0); c0 = j->c_end;
         j->seed = seed; j->sweep0 = sweep0; j->n_sweeps = n_sweeps; j->record = record;
         j->T = T; j->spins = spins; j->k = k; j->m = m; j->hist = hist; j->sabs = sabs;
