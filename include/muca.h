@@ -57,19 +57,30 @@ typedef enum {
     MUCA_ESTATE = -4
 } muca_status;
 
-enum { MUCA_ISING = 0, MUCA_POTTS = 1 };
+enum { MUCA_ISING = 0, MUCA_POTTS = 1, MUCA_ISING_MAG = 2 };
 enum { MUCA_REC_NONE = 0, MUCA_REC_MUCA = 1, MUCA_REC_PROD = 2 };
 
 /* One problem: a model on one lattice with n_chains chains sharing lnW.
  * Ising: L even, 4 <= L <= 256, q ignored.  Potts: 3 <= L <= 256, 3 <= q <= 8.
  * 1 <= n_chains <= 1<<20.  seed keys the generator (Sec. 2: same weights,
- * different random numbers per chain). */
+ * different random numbers per chain).
+ *
+ * MUCA_ISING_MAG is the multimagnetic Ising ensemble of Sec. 4: the Ising
+ * lattice (same L rules, same random numbers and sweep order) sampled with
+ * exp(-beta E) W(M), the weights over the magnetization M at the fixed inverse
+ * temperature beta (0 <= beta <= 10; ignored by the other models).  Its bins
+ * are m = number of up spins = (M + N) / 2, m = 0..N (N+1 bins, all
+ * reachable), where the energy models use k = 0..2N.  A flip that changes k by
+ * dk and m by dm is accepted with probability
+ * min(1, exp((lnW[m+dm] - lnW[m]) - beta * 2 dk)), through the same integer
+ * threshold rule as below (delta evaluated in that order, in IEEE double). */
 typedef struct {
     int32_t model;
     int32_t q;
     int32_t L;
     int32_t n_chains;
     uint64_t seed;
+    double beta;
 } muca_problem;
 
 /* Launch and iteration options; zero means "default / autotune".
@@ -148,7 +159,9 @@ muca_status mucaSetLogWeights(muca_ctx ctx, int32_t prob, const double *lnW, int
  * per chain per sweep). */
 muca_status mucaSweep(muca_ctx ctx, int64_t n_sweeps, int32_t record);
 
-/* Merges the per-chain histograms (H = sum_i H_i, Sec. 2) and clears them.
+/* Bins: "k" below stands for the problem's bin index (m for MUCA_ISING_MAG).
+ *
+ * Merges the per-chain histograms (H = sum_i H_i, Sec. 2) and clears them.
  * update = 1 also applies lnW <- lnW - ln H where H > 0 and rebuilds the
  * tables.  Writes one muca_iter_stats per problem to out (may be NULL).
  * Synchronises the stream. */
@@ -163,7 +176,8 @@ muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out);
  * (accumulated by MUCA_REC_PROD sweeps since the last mucaClearProduction)
  * to n_betas inverse temperatures.  Outputs (host arrays of n_betas doubles,
  * caller-owned): <E>/N, C_V = beta^2 (<E^2> - <E>^2)/N and <|M|>/N (Ising;
- * NaN for Potts).  Runs on the device in double precision; synchronises. */
+ * NaN for Potts).  Runs on the device in double precision; synchronises.
+ * MUCA_EINVAL for a MUCA_ISING_MAG problem (its weights are not over E). */
 muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_t n_betas,
                          double *e_per_site, double *c_v, double *abs_m_per_site);
 
@@ -220,6 +234,10 @@ muca_status mucaInterfaceTension(muca_ctx ctx, int32_t prob, double beta_lo, dou
  *   MUCA_GET_PROD_ABSM int64[2N+1]     merged production |M| sums
  *   MUCA_GET_SWEEP    uint32[1]        sweeps done since init
  *   MUCA_GET_REACH    uint8[2N+1]      reachable-bin mask
+ * For MUCA_ISING_MAG every per-bin item has N+1 bins (m = 0..N), T is
+ * uint32[N+1][10] with column j + 5u (u = 1 when the spin to flip is up, so
+ * that m' = m - 1, else m' = m + 1; the flip changes k by dk = 2j - 4), and
+ * MUCA_GET_PROD_ABSM holds the sums of k (unsatisfied bonds) per m.
  * Synchronises the stream. */
 enum {
     MUCA_GET_H = 0, MUCA_GET_LNW = 1, MUCA_GET_T = 2, MUCA_GET_SPINS = 3, MUCA_GET_K = 4,

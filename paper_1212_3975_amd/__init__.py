@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmuca.so")
 
-ISING, POTTS = 0, 1
+ISING, POTTS, ISING_MAG = 0, 1, 2
 REC_NONE, REC_MUCA, REC_PROD = 0, 1, 2
 GET_H, GET_LNW, GET_T, GET_SPINS, GET_K, GET_M, GET_CHAIN_H, GET_PROD_CNT, GET_PROD_ABSM, GET_SWEEP, GET_REACH = range(11)
 
@@ -34,7 +34,7 @@ class MucaError(RuntimeError):
 
 class Problem(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("q", ctypes.c_int32), ("L", ctypes.c_int32),
-                ("n_chains", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("n_chains", ctypes.c_int32), ("seed", ctypes.c_uint64), ("beta", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -141,7 +141,8 @@ def _dptr(a: np.ndarray, t):
 def make_problems(problems) -> "ctypes.Array":
     arr = (Problem * len(problems))()
     for i, p in enumerate(problems):
-        arr[i] = Problem(int(p.model), int(getattr(p, "q", 2)), int(p.L), int(p.n_chains), int(p.seed))
+        arr[i] = Problem(int(p.model), int(getattr(p, "q", 2)), int(p.L), int(p.n_chains), int(p.seed),
+                         float(getattr(p, "beta", 0.0)))
     return arr
 
 
@@ -241,7 +242,8 @@ class Muca:
     def _dims(self, prob):
         p = self.problems[prob]
         N = p.L * p.L
-        return N, 2 * N + 1, p.n_chains
+        # bins: k = 0..2N, or m = 0..N up spins for the multimagnetic ensemble
+        return N, (N + 1 if p.model == ISING_MAG else 2 * N + 1), p.n_chains
 
     def H(self, prob=0):
         return self._get(GET_H, prob, np.int64, self._dims(prob)[1])
@@ -250,7 +252,8 @@ class Muca:
         return self._get(GET_LNW, prob, np.float64, self._dims(prob)[1])
 
     def table(self, prob=0):
-        return self._get(GET_T, prob, np.uint32, (self._dims(prob)[1], 9))
+        cols = 10 if self.problems[prob].model == ISING_MAG else 9
+        return self._get(GET_T, prob, np.uint32, (self._dims(prob)[1], cols))
 
     def spins(self, prob=0):
         """Spins as [C][N] (chain-major) for comparison; the device keeps [N][C]."""

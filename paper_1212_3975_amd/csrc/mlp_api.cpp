@@ -224,6 +224,7 @@ muca_status mucaMlpAddWeights(muca_mlp m, muca_ctx ctx, int32_t prob) {
     muca_problem def;
     muca_status st = mucaProblemInfo(ctx, prob, &def);
     if (st) return mfail(m, st, "%s", mucaLastError(ctx));
+    if (def.model == MUCA_ISING_MAG) return mfail(m, MUCA_EINVAL, "the network learns weights over the energy only");
     const int N = def.L * def.L, nb = 2 * N + 1;
     std::vector<double> lnW(nb);
     std::vector<uint8_t> reach(nb);
@@ -307,6 +308,7 @@ muca_status mucaMlpSetLogWeights(muca_mlp m, muca_ctx ctx, int32_t prob) {
     muca_problem def;
     muca_status st = mucaProblemInfo(ctx, prob, &def);
     if (st) return mfail(m, st, "%s", mucaLastError(ctx));
+    if (def.model == MUCA_ISING_MAG) return mfail(m, MUCA_EINVAL, "the network predicts weights over the energy only");
     const int N = def.L * def.L, nb = 2 * N + 1;
     if (nb > m->max_n) return mfail(m, MUCA_EINVAL, "problem has %d bins > capacity %d", nb, m->max_n);
     std::vector<uint8_t> reach(nb);

@@ -41,8 +41,12 @@ uint32_t threshold(double delta) {
 }
 
 // Bins that can occur: Ising (even L) every even k except 2 and 2N-2; Potts
-// (q >= 3) every k except 1, 2, 3 and 5.
+// (q >= 3) every k except 1, 2, 3 and 5; multimagnetic every m = 0..N.
 void reachable_mask(int model, int N, std::vector<uint8_t> &mask) {
+    if (model == MUCA_ISING_MAG) {
+        mask.assign(N + 1, 1);
+        return;
+    }
     mask.assign(2 * N + 1, 1);
     if (model == MUCA_ISING) {
         for (int k = 0; k <= 2 * N; ++k)
@@ -133,9 +137,11 @@ muca_status validate(const muca_problem *pr, int32_t n, const muca_options *o) {
     if (!pr || n <= 0 || n > 64) return fail(nullptr, MUCA_EINVAL, "need 1..64 problems");
     for (int i = 0; i < n; ++i) {
         const muca_problem &p = pr[i];
-        if (p.model == MUCA_ISING) {
+        if (p.model == MUCA_ISING || p.model == MUCA_ISING_MAG) {
             if (p.L < 4 || p.L > 256 || (p.L & 1))
                 return fail(nullptr, MUCA_EINVAL, "problem %d: Ising needs even L in 4..256", i);
+            if (p.model == MUCA_ISING_MAG && !(p.beta >= 0.0 && p.beta <= 10.0))
+                return fail(nullptr, MUCA_EINVAL, "problem %d: multimagnetic beta must be in [0, 10]", i);
         } else if (p.model == MUCA_POTTS) {
             if (p.L < 3 || p.L > 256) return fail(nullptr, MUCA_EINVAL, "problem %d: Potts needs L in 3..256", i);
             if (p.q < 3 || p.q > 8) return fail(nullptr, MUCA_EINVAL, "problem %d: Potts needs q in 3..8", i);
@@ -186,11 +192,12 @@ Layout plan_layout(const muca_problem *pr, int32_t n, const muca_options &o) {
     for (int i = 0; i < n; ++i) {
         ProbHost h;
         h.def = pr[i];
-        if (h.def.model == MUCA_ISING) h.def.q = 2;
+        if (h.def.model != MUCA_POTTS) h.def.q = 2;
+        if (h.def.model != MUCA_ISING_MAG) h.def.beta = 0.0;
         h.N = pr[i].L * pr[i].L;
-        h.nbins = 2 * h.N + 1;
-        h.trows = (h.def.model == MUCA_ISING) ? h.N + 1 : h.nbins;
-        h.tcols = (h.def.model == MUCA_ISING) ? 5 : 9;
+        h.nbins = (h.def.model == MUCA_ISING_MAG) ? h.N + 1 : 2 * h.N + 1;
+        h.trows = (h.def.model == MUCA_POTTS) ? h.nbins : h.N + 1;
+        h.tcols = (h.def.model == MUCA_ISING) ? 5 : (h.def.model == MUCA_ISING_MAG) ? 10 : 9;
         const size_t C = (size_t)pr[i].n_chains;
         h.off_spins = take((size_t)h.N * C);
         h.off_k = take(4 * C);
@@ -305,7 +312,20 @@ void correction(ProbHost &p, const int64_t *H) {
 // Device-layout table of one problem (see muca_device.h).
 void device_table(const ProbHost &p, uint32_t *out) {
     const int n = p.nbins;
-    if (p.def.model == MUCA_ISING) {
+    if (p.def.model == MUCA_ISING_MAG) {
+        // row m (up spins), column j + 5u: an up spin (u = 1) goes to m - 1,
+        // a down spin to m + 1; the flip changes k by dk = 2j - 4, E by 2 dk
+        const double beta = p.def.beta;
+        for (int m = 0; m < n; ++m)
+            for (int u = 0; u < 2; ++u) {
+                const int t = u ? m - 1 : m + 1;
+                for (int j = 0; j < 5; ++j) {
+                    const int dk = 2 * j - 4;
+                    out[m * 10 + j + 5 * u] =
+                        (t >= 0 && t < n) ? threshold((p.lnW[t] - p.lnW[m]) - beta * (double)(2 * dk)) : 0u;
+                }
+            }
+    } else if (p.def.model == MUCA_ISING) {
         for (int r = 0; r < p.trows; ++r) {
             const int k = 2 * r;
             for (int j = 0; j < 5; ++j) {
@@ -915,6 +935,7 @@ muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_
         return fail(ctx, MUCA_EINVAL, "n_betas must be 1..%d", kMaxBetas);
     if (!e_per_site || !c_v || !abs_m_per_site) return fail(ctx, MUCA_EINVAL, "NULL output");
     ProbHost &p = ctx->probs[prob];
+    if (p.def.model == MUCA_ISING_MAG) return fail(ctx, MUCA_EINVAL, "reweighting in beta needs weights over E");
     if (!p.prod_data) return fail(ctx, MUCA_ESTATE, "no production data");
     // merge the production accumulators (counts into H, |M| sums into S), keep them
     HIPCHECK(ctx, launch_merge(ctx->d_probs, ctx->d_merge, (int)ctx->merge_items.size(), 1, 0, ctx->stream));
@@ -942,6 +963,7 @@ muca_status mucaInterfaceTension(muca_ctx ctx, int32_t prob, double beta_lo, dou
     muca_status st = check_prob(ctx, prob);
     if (st) return st;
     ProbHost &p = ctx->probs[prob];
+    if (p.def.model == MUCA_ISING_MAG) return fail(ctx, MUCA_EINVAL, "the interface analysis needs weights over E");
     if (!p.prod_data) return fail(ctx, MUCA_ESTATE, "no production data");
     // merge the production accumulators (counts into H), keep them
     HIPCHECK(ctx, launch_merge(ctx->d_probs, ctx->d_merge, (int)ctx->merge_items.size(), 1, 0, ctx->stream));
@@ -979,6 +1001,12 @@ muca_status mucaGet(muca_ctx ctx, int32_t what, int32_t prob, void *dst, size_t 
         std::memcpy(dst, p.lnW.data(), 8 * nb);
         return MUCA_OK;
     case MUCA_GET_T: {
+        if (p.def.model == MUCA_ISING_MAG) {
+            if ((st = need(4 * nb * 10))) return st;
+            HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+            device_table(p, (uint32_t *)dst);   // the device layout is [m][10] already
+            return MUCA_OK;
+        }
         if ((st = need(4 * nb * 9))) return st;
         HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
         uint32_t *T = (uint32_t *)dst;
@@ -1081,7 +1109,7 @@ muca_status mucaCheckpoint(muca_ctx ctx, void *blob, size_t *bytes) {
     }
     if (*bytes < need) return fail(ctx, MUCA_EINVAL, "checkpoint needs %zu bytes", need);
     uint8_t *o = (uint8_t *)blob;
-    CkptHeader h{kMagic, 1, ctx->probs.size(), ctx->sweep};
+    CkptHeader h{kMagic, 2, ctx->probs.size(), ctx->sweep};   // 2: problems carry beta
     std::memcpy(o, &h, sizeof h);
     o += sizeof h;
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
@@ -1113,7 +1141,7 @@ muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes) {
     CkptHeader h;
     std::memcpy(&h, in, sizeof h);
     in += sizeof h;
-    if (h.magic != kMagic || h.version != 1 || h.n_problems != ctx->probs.size())
+    if (h.magic != kMagic || h.version != 2 || h.n_problems != ctx->probs.size())
         return fail(ctx, MUCA_EINVAL, "not a checkpoint of this context");
     // validate every problem before touching state
     const uint8_t *scan = in;
@@ -1121,7 +1149,8 @@ muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes) {
         muca_problem def;
         std::memcpy(&def, scan, sizeof def);
         if (def.model != p.def.model || def.L != p.def.L || def.n_chains != p.def.n_chains ||
-            def.seed != p.def.seed || (def.model == MUCA_POTTS && def.q != p.def.q))
+            def.seed != p.def.seed || (def.model == MUCA_POTTS && def.q != p.def.q) ||
+            (def.model == MUCA_ISING_MAG && def.beta != p.def.beta))
             return fail(ctx, MUCA_EINVAL, "checkpoint problem differs from the context");
         const size_t C = p.def.n_chains;
         scan += sizeof(muca_problem) + (size_t)p.N * C + 8 * C + 8 * (size_t)p.nbins + 4 * (size_t)p.nbins * C;

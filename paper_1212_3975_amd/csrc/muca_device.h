@@ -7,6 +7,7 @@ namespace muca {
 
 constexpr int kIsing = 0;
 constexpr int kPotts = 1;
+constexpr int kIsingMag = 2;   // Ising with weights over the magnetization at fixed beta
 constexpr int kRecNone = 0;
 constexpr int kRecMuca = 1;
 constexpr int kRecProd = 2;

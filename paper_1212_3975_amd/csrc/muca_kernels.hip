@@ -48,7 +48,7 @@ __global__ void init_kernel(ProbDev p, int chain_begin, int n_chains) {
         const int c = chain_begin + (int)(t % n_chains);
         const uint4 b = philox4x32_10((uint32_t)i, 0u, (uint32_t)c, 1u, p.seed_lo, p.seed_hi);
         uint8_t s;
-        if (p.model == kIsing)
+        if (p.model != kPotts)
             s = (uint8_t)(b.x >> 31);
         else
             s = (uint8_t)(((uint64_t)b.x * (uint64_t)p.q) >> 32);
@@ -73,7 +73,7 @@ __global__ void energy_kernel(ProbDev p) {
         }
     }
     p.k[c] = k;
-    p.m[c] = (p.model == kIsing) ? m : 0;
+    p.m[c] = (p.model != kPotts) ? m : 0;
 }
 
 // ------------------------------------------------------------------ sweep
@@ -118,7 +118,7 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
     }
     const int spn = p.spin_lds ? round_up((p.N + 3) / 4 * it.spin_stride * 4, 16) : 0;
     l.off_ring = l.off_spin + spn;
-    const int words = (p.model == kIsing) ? 1 : 2;
+    const int words = (p.model == kPotts) ? 2 : 1;
     const int ring = n_producer_waves > 0 ? 2 * kChunkSites * it.spin_stride * 4 * words : 0;
     l.total = l.off_ring + ring;
     return l;
@@ -170,7 +170,7 @@ __device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring,
     const uint32_t sweep = sweep0 + (uint32_t)sw;
     const int i0 = chunk * kChunkSites;
     const int i1 = min(p.N, i0 + kChunkSites);
-    constexpr int SPB = (MODEL == kIsing) ? 4 : 2;   // sites per Philox block
+    constexpr int SPB = (MODEL == kPotts) ? 2 : 4;   // sites per Philox block
     const int nblk = (i1 - i0 + SPB - 1) / SPB;
     const int total = nblk * it.nchains;
     const int ls = it.spin_stride;
@@ -182,7 +182,7 @@ __device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring,
         const uint4 blk = philox4x32_10((uint32_t)(i0 / SPB + b), sweep, (uint32_t)(it.chain0 + lane), 0u,
                                         p.seed_lo, p.seed_hi);
         uint4 o;
-        if (MODEL == kIsing) {
+        if (MODEL != kPotts) {
             o = make_uint4(min(blk.x, 0xFFFFFFFEu), min(blk.y, 0xFFFFFFFEu), min(blk.z, 0xFFFFFFFEu),
                            min(blk.w, 0xFFFFFFFEu));
         } else {
@@ -195,8 +195,9 @@ __device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring,
 
 // Walker state of one lane (one chain) in the generic walker.
 struct WalkState {
-    int row;        // table row: k/2 (Ising) or k (Potts)
+    int row;        // table row: k/2 (Ising), k (Potts), up spins (multimagnetic)
     int m;          // Ising magnetisation
+    int k;          // unsatisfied bonds (multimagnetic only; the row holds k otherwise)
     int x, y, i;    // current site
 };
 
@@ -211,13 +212,21 @@ __device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN
     const uint8_t s = S.ld(i);
     const uint8_t a = S.ld(il), b = S.ld(ir), c = S.ld(iu), d = S.ld(id);
     uint8_t snew;
-    int col, drow;
+    int col, drow, dk = 0;
     if (MODEL == kIsing) {
         snew = s ^ 1u;
         const int nd = (a != s) + (b != s) + (c != s) + (d != s);
         // dk = 4 - 2 nd bonds; table row moves by dk/2 = 2 - nd, column 4 - nd
         col = 4 - nd;
         drow = 2 - nd;
+    } else if (MODEL == kIsingMag) {
+        snew = s ^ 1u;
+        const int nd = (a != s) + (b != s) + (c != s) + (d != s);
+        // row: up spins, -1 when an up spin flips, +1 for a down spin; column
+        // 4 - nd (+5 for an up spin); the flip changes k by 4 - 2 nd
+        col = 4 - nd + (s ? 5 : 0);
+        drow = s ? -1 : 1;
+        dk = 4 - 2 * nd;
     } else {
         const uint32_t q = (uint32_t)p.q;
         uint32_t v = (uint32_t)s + 1u + tq;
@@ -227,12 +236,13 @@ __device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN
         drow = after - before;
         col = drow + 4;
     }
-    const uint32_t t = tab[st.row * (MODEL == kIsing ? 5 : 9) + col];
+    const uint32_t t = tab[st.row * (MODEL == kIsing ? 5 : MODEL == kIsingMag ? 10 : 9) + col];
     const bool acc = u < t;   // u arrives as min(u, 0xfffffffe)
     if (acc) {
         S.st(i, snew);
         st.row += drow;
-        if (MODEL == kIsing) st.m += snew ? 2 : -2;
+        if (MODEL != kPotts) st.m += snew ? 2 : -2;
+        if (MODEL == kIsingMag) st.k += dk;
     }
     st.i = i + 1;
     st.x = x + 1;
@@ -261,7 +271,7 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
     }
     const uint32_t chain = (uint32_t)(it.chain0 + lane);
     if (OWN_RNG) {
-        if (MODEL == kIsing) {
+        if (MODEL != kPotts) {
             // N is a multiple of 4 for even L: whole blocks of four sites
             for (int i = i0; i < i1; i += 4) {
                 const uint4 b = philox4x32_10((uint32_t)(i >> 2), sweep, chain, 0u, p.seed_lo, p.seed_hi);
@@ -283,7 +293,7 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
         }
     } else {
         const int ls = it.spin_stride;
-        if (MODEL == kIsing) {
+        if (MODEL != kPotts) {
             const uint4 *r = ring + (t & 1) * (kChunkSites / 4) * ls + lane;
             for (int i = i0; i < i1; i += 4) {
                 const uint4 w = r[((i - i0) >> 2) * ls];
@@ -302,10 +312,13 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
         }
     }
     if (i1 == p.N && record != kRecNone) {
-        const int k = (MODEL == kIsing) ? 2 * st.row : st.row;
+        // bin: k (energy models) or up spins (multimagnetic); production adds
+        // |M| per energy bin, or the bond count k per magnetization bin
+        const int b = (MODEL == kIsing) ? 2 * st.row : st.row;
         const int c = it.chain0 + lane;
-        p.hist[(int64_t)k * p.C + c] += 1;
-        if (record == kRecProd) p.sabs[(int64_t)k * p.C + c] += (int64_t)(st.m < 0 ? -st.m : st.m);
+        p.hist[(int64_t)b * p.C + c] += 1;
+        if (record == kRecProd)
+            p.sabs[(int64_t)b * p.C + c] += (MODEL == kIsingMag) ? (int64_t)st.k : (int64_t)(st.m < 0 ? -st.m : st.m);
     }
 }
 
@@ -836,11 +849,13 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
         WalkState st;
         st.row = 0;
         st.m = 0;
+        st.k = 0;
         st.x = st.y = st.i = 0;
         if (active) {
             const int k = p.k[it.chain0 + lane];
-            st.row = (MODEL == kIsing) ? (k >> 1) : k;
             st.m = p.m[it.chain0 + lane];
+            st.k = k;
+            st.row = (MODEL == kIsing) ? (k >> 1) : (MODEL == kIsingMag) ? (st.m + p.N) / 2 : k;
         }
         if (l.n_producer_waves == 0) {
             __syncthreads();
@@ -865,7 +880,7 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
             }
         }
         if (active) {
-            p.k[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : st.row;
+            p.k[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : (MODEL == kIsingMag) ? st.k : st.row;
             p.m[it.chain0 + lane] = st.m;
         }
     }
@@ -892,6 +907,14 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepLaunch l) {
         } else {
             if (p.table_lds) run_item<kIsing, false, true>(p, it, lds, l, sweep0);
             else run_item<kIsing, false, false>(p, it, lds, l, sweep0);
+        }
+    } else if (p.model == kIsingMag) {
+        if (p.spin_lds) {
+            if (p.table_lds) run_item<kIsingMag, true, true>(p, it, lds, l, sweep0);
+            else run_item<kIsingMag, true, false>(p, it, lds, l, sweep0);
+        } else {
+            if (p.table_lds) run_item<kIsingMag, false, true>(p, it, lds, l, sweep0);
+            else run_item<kIsingMag, false, false>(p, it, lds, l, sweep0);
         }
     } else {
         if (p.spin_lds) {

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from conftest import gpu_available
-from workloads import C1, ISING, POTTS, Problem
+from workloads import C1, ISING, ISING_MAG, POTTS, Problem
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -20,7 +20,7 @@ def _pm():
 
 def _orc(prob: Problem, chain0=0, n=None):
     return oracle.OracleRun(prob.model, prob.L, n if n is not None else prob.n_chains, prob.seed, q=prob.q,
-                            chain0=chain0)
+                            chain0=chain0, beta=prob.beta)
 
 
 def _orc_iteration(orc, n_sweeps):
@@ -29,7 +29,7 @@ def _orc_iteration(orc, n_sweeps):
     per_chain = orc.hist.copy()
     H = orc.merged()
     oracle.lib().orc_recursion(orc.n_bins, H, orc.lnW)
-    orc.T = oracle.build_table(orc.lnW)
+    orc.T = orc._table()
     orc.hist[:] = 0
     return per_chain, H
 
@@ -274,3 +274,52 @@ def test_interface_tension_of_a_production_run():
     assert got["k_peaks"] == ks
     # a first-order double peak: ordered peak at low k, disordered at high k
     assert ks[0] < ks[1] < ks[2] and 0.0 < got["sigma"] < 0.2
+
+
+
+MAG_PROBS = [Problem(ISING_MAG, 6, 100, 21, beta=0.66), Problem(ISING_MAG, 16, 40, 22, beta=0.4407),
+             Problem(ISING_MAG, 12, 65, 23, beta=1.1)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "-".join(f"{k[:4]}{v}" for k, v in c.items()))
+@pytest.mark.parametrize("prob", MAG_PROBS, ids=lambda p: f"mag L{p.L}C{p.n_chains}b{p.beta}")
+def test_multimagnetic_bit_exact(prob, cfg):
+    """Multimagnetic Ising (weights over M at fixed beta, Sec. 4) in every
+    launch configuration: spins, k, M, per-chain and merged histograms over m,
+    weights and the two-factor tables equal the oracle's."""
+    pm = _pm()
+    print("case", prob, cfg, flush=True)
+    with pm.Muca([prob], **cfg) as ctx:
+        assert ctx.launch_info()["fast_walker"] == 0
+        orc = _orc(prob)
+        assert ctx.table().shape == (prob.L * prob.L + 1, 10)
+        assert np.array_equal(ctx.table(), orc.T)
+        assert np.array_equal(ctx.reachable(), orc.mask)
+        _compare_iterations(ctx, orc, 4, 150)
+
+
+def test_multimagnetic_batched_with_energy_models_and_production():
+    """A multimagnetic problem batched with Ising and Potts problems in one
+    launch; then production counts and the k sums per m bin."""
+    pm = _pm()
+    probs = [Problem(ISING_MAG, 8, 48, 31, beta=0.66), Problem(ISING, 8, 40, 32), Problem(POTTS, 6, 24, 33, q=8)]
+    with pm.Muca(probs, correction=1) as ctx:
+        orcs = [_orc(p) for p in probs]
+        for it in range(3):
+            print(f"  iteration {it}", flush=True)
+            ctx.iterate(200)
+            for j, o in enumerate(orcs):
+                H, _, _ = o.iterate(200, correct=True)
+                assert np.array_equal(ctx.H(j), H)
+                assert _same_bits(ctx.lnW(j), o.lnW)
+                assert np.array_equal(ctx.spins(j), o.spins)
+                assert np.array_equal(ctx.table(j), o.T)
+        ctx.sweep(100, pm.REC_NONE)
+        ctx.sweep(300, pm.REC_PROD)
+        cnt, ksum = ctx.prod_counts(0), ctx.prod_absm(0)
+        for o in orcs:
+            o.sweeps(100, oracle.REC_NONE)
+        ocnt, oks = orcs[0].production(0, 300)
+        assert np.array_equal(cnt, ocnt) and np.array_equal(ksum, oks)
+        with pytest.raises(pm.MucaError, match="weights over E"):
+            ctx.reweight(0, [0.3, 0.4])

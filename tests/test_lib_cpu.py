@@ -38,8 +38,8 @@ def _status(problems, **opt):
 
 
 class P:
-    def __init__(self, model, L, n_chains, seed=1, q=2):
-        self.model, self.L, self.n_chains, self.seed, self.q = model, L, n_chains, seed, q
+    def __init__(self, model, L, n_chains, seed=1, q=2, beta=0.0):
+        self.model, self.L, self.n_chains, self.seed, self.q, self.beta = model, L, n_chains, seed, q, beta
 
 
 def test_workspace_size_and_validation():
@@ -51,7 +51,11 @@ def test_workspace_size_and_validation():
     assert _status([P(1, 2, 4, q=8)])[0] == -1     # L < 3
     assert _status([P(1, 8, 4, q=9)])[0] == -1     # q > 8
     assert _status([P(0, 8, 0)])[0] == -1          # no chains
-    assert _status([P(2, 8, 4)])[0] == -1          # unknown model
+    assert _status([P(3, 8, 4)])[0] == -1          # unknown model
+    assert _status([P(2, 8, 4, beta=0.66)])[0] == 0           # multimagnetic Ising
+    assert _status([P(2, 7, 4, beta=0.66)])[0] == -1          # odd L
+    assert _status([P(2, 8, 4, beta=-0.1)])[0] == -1          # beta < 0
+    assert _status([P(2, 8, 4, beta=float("nan"))])[0] == -1  # beta not a number
     assert _status([P(0, 8, 4)], chains_per_wg=12)[0] == -1
     msg = pm.lib().mucaLastError(None).decode()
     assert "chains_per_wg" in msg

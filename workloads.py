@@ -15,6 +15,7 @@ from typing import List, Tuple
 
 ISING = 0
 POTTS = 1
+ISING_MAG = 2   # Ising with multimagnetic weights over M at a fixed beta (Sec. 4)
 
 
 @dataclass(frozen=True)
@@ -25,6 +26,7 @@ class Problem:
     n_chains: int       # independent Markov chains sharing lnW
     seed: int           # 64-bit key of the counter-based generator
     q: int = 2          # number of Potts states (2 for Ising)
+    beta: float = 0.0   # fixed inverse temperature of the multimagnetic ensemble
 
     @property
     def N(self) -> int:
@@ -32,8 +34,9 @@ class Problem:
 
     @property
     def n_bins(self) -> int:
-        # bins are indexed by the number of unsatisfied bonds, 0..2N
-        return 2 * self.N + 1
+        # bins are indexed by the number of unsatisfied bonds, 0..2N, or for
+        # the multimagnetic ensemble by the number of up spins, 0..N
+        return self.N + 1 if self.model == ISING_MAG else 2 * self.N + 1
 
 
 @dataclass(frozen=True)
