@@ -61,14 +61,15 @@ def cpu_baseline(prob, sweeps: int, n_chains: int):
     same workload: n_chains chains for `sweeps` sweeps."""
     import oracle
     threads = oracle.default_threads()
-    orc = oracle.OracleRun(prob.model, prob.L, n_chains, prob.seed, q=prob.q, n_threads=threads)
+    orc = oracle.OracleRun(prob.model, prob.L, n_chains, prob.seed, q=prob.q, n_threads=threads,
+                           beta=getattr(prob, "beta", 0.0))
     t0 = time.perf_counter()
     orc.sweeps(sweeps, oracle.REC_MUCA)
     dt = time.perf_counter() - t0
     ups = n_chains * sweeps * prob.N / dt
     return {"value": round(ups / 1e9, 4), "unit": "G/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_chains} chains x {sweeps} recorded sweeps of "
-                      f"{'Ising' if prob.model == 0 else str(prob.q) + '-state Potts'} L={prob.L} "
+                      f"{['Ising', str(prob.q) + '-state Potts', 'multimagnetic Ising'][prob.model]} L={prob.L} "
                       f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
 
 
@@ -108,7 +109,7 @@ def main():
     ap.add_argument("--fixed", action="store_true",
                     help="skip tuning: 16 chains per workgroup, 3 producer waves, LDS placement")
     ap.add_argument("--no-extra", action="store_true", help="skip the production and reweighting leg")
-    ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed"])
+    ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed", "mag32"])
     ap.add_argument("--graph", action="store_true", help="run each iteration as one HIP graph launch")
     ap.add_argument("--scan-chains", type=int, default=0, metavar="L",
                     help="instead of the benchmark: sweep throughput of Ising L x L versus the number of chains")
@@ -123,7 +124,7 @@ def main():
 
     import torch
     import paper_1212_3975_amd as pm
-    from workloads import C2, C3, C4, ISING, Problem
+    from workloads import C2, C3, C4, C_MAG, ISING, Problem
 
     if args.scan_chains:
         scan_chains(args.scan_chains, pm, torch, Problem, ISING)
@@ -135,7 +136,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    plan = {"ising64": C2, "potts32": C3, "mixed": C4}[args.workload]
+    plan = {"ising64": C2, "potts32": C3, "mixed": C4, "mag32": C_MAG}[args.workload]
     probs = list(plan.problems)
     prob = probs[0]
     M = plan.sweeps_per_iter
@@ -146,7 +147,7 @@ def main():
     ctx = pm.Muca(probs, device="cuda:0", **opts)
     launch = [ctx.launch_info(i) for i in range(len(probs))]
     updates_per_step = sum(p.n_chains * p.N for p in probs) * M
-    ops_per_update = OPS_PER_ISING_UPDATE if args.workload == "ising64" else None
+    ops_per_update = OPS_PER_ISING_UPDATE if args.workload in ("ising64", "mag32") else None
 
     def step():
         if args.graph:
@@ -196,6 +197,8 @@ def main():
                    "(sweep + merge + recursion + tables)",
         "mixed": "Ising L in {16,24,32,48,64} and 8-Potts L in {8,16,24,32}, 512 chains each, one launch, "
                  "one weight iteration of 2000 sweeps",
+        "mag32": "multimagnetic 2D Ising L=32 at beta = 1.5 beta_0 (weights over M), 4096 chains, one weight "
+                 "iteration of 2000 sweeps (sweep + merge + recursion + tables)",
     }[args.workload]
 
     out = {

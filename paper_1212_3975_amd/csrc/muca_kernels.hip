@@ -128,11 +128,13 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     return lds_plan(p, it, n_producer_waves).total;
 }
 
-// The fast Ising walker has compiled shapes for these sizes and needs both
+// The fast Ising walker (and its multimagnetic variant) has compiled shapes
+// for these sizes and needs both
 // arrays in LDS and producer waves.
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves) {
     const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32 || p.L == 48 || p.L == 64;
-    return p.model == kIsing && size_ok && p.spin_lds && p.table_lds && n_producer_waves > 0;
+    return (p.model == kIsing || p.model == kIsingMag) && size_ok && p.spin_lds && p.table_lds &&
+           n_producer_waves > 0;
 }
 // The fast Potts walker: q = 8, compiled sizes, both arrays in LDS, producers.
 __host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves) {
@@ -372,10 +374,10 @@ __device__ __forceinline__ int32_t sbyte(uint32_t v, int j) { return (int32_t)(i
 struct FastBulk {
     uint32_t cur;      // old spins of the dword
     uint32_t a0, a1;   // bytes: column byte offset 16 - 4D for D0 / D1
-    uint32_t e0, e1;   // bytes (int8): row byte step 40 - 20D for D0 / D1
+    uint32_t e0, e1;   // bytes (int8): row byte step 40 - 20D for D0 / D1 (multimagnetic: +-40)
 };
 
-template <bool ROW_START>
+template <bool ROW_START, bool MAG = false>
 __device__ __forceinline__ FastBulk fast_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn) {
     // right neighbours: bytes cur1 cur2 cur3 nxt0; left (old): prv3 cur0 cur1 cur2
     const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
@@ -391,14 +393,43 @@ __device__ __forceinline__ FastBulk fast_bulk(uint32_t cur, uint32_t prv, uint32
     b.cur = cur;
     b.a0 = __builtin_amdgcn_perm(0u, 0x04080C10u, d0);           // 16,12,8,4,0
     b.a1 = __builtin_amdgcn_perm(0u, 0x04080C10u, d1);
-    b.e0 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d0);        // 40,20,0,-20,-40
-    b.e1 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d1);
+    if (MAG) {
+        // multimagnetic rows are up-spin counts of 40 bytes (ten columns): the
+        // row moves by -40 for an up spin and +40 for a down one, whatever the
+        // left neighbour did, and an up spin reads the columns 5..9
+        const uint32_t s20 = __builtin_amdgcn_perm(0u, 0x00001400u, cur);   // 0 / 20 per byte
+        b.a0 += s20;
+        b.a1 += s20;
+        b.e0 = __builtin_amdgcn_perm(0u, 0x0000D828u, cur);                 // +40 / -40
+        b.e1 = b.e0;
+    } else {
+        b.e0 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d0);        // 40,20,0,-20,-40
+        b.e1 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d1);
+    }
     return b;
 }
 
+// Bond count k of a lane-major LDS lattice (right and down bond of every site).
 template <int L>
+__device__ __forceinline__ int lattice_bonds(uint32_t sb) {
+    constexpr int W = L / 4;
+    int k = 0;
+    for (int y = 0; y < L; ++y) {
+        const uint32_t r = sb + (uint32_t)(y * W) * 4u, rd = sb + (uint32_t)((y + 1 == L ? 0 : y + 1) * W) * 4u;
+        for (int w = 0; w < W; ++w) {
+            const uint32_t cur = lds_ld(r + 4u * w), nxt = lds_ld(r + 4u * (w + 1 == W ? 0 : w + 1));
+            k += __builtin_popcount(cur ^ __builtin_amdgcn_alignbyte(nxt, cur, 1)) +
+                 __builtin_popcount(cur ^ lds_ld(rd + 4u * w));
+        }
+    }
+    return k;
+}
+
+template <int L, bool MAG>
 __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
+    // table row bytes: Ising rows k/2 of five words, multimagnetic rows m of ten
+    constexpr uint32_t RB = MAG ? 40u : 20u;
     constexpr int W = L / 4;                  // dwords per row
     constexpr int NW = L * L / 4;             // dwords per lattice
     constexpr int RPC = fast_rows_per_chunk(L);
@@ -435,10 +466,10 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     FastBulk nb{0, 0, 0, 0, 0};
     if (active) {
         const int k = p.k[it.chain0 + lane];
-        R = tab0 + 20u * (uint32_t)(k >> 1);
+        R = MAG ? tab0 + RB * (uint32_t)((p.m[it.chain0 + lane] + L * L) / 2) : tab0 + RB * (uint32_t)(k >> 1);
         C = R;
         const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
-        nb = fast_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1));
+        nb = fast_bulk<true, MAG>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1));
         tA = lds_ld(R + ubyte(nb.a0, 0));
         tB = tA;
     }
@@ -490,12 +521,13 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                         if (w + 1 < W) {
                             const uint32_t c1 = nxt_cache;   // old dword w+1
                             const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
-                            nb = fast_bulk<false>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)), lds_ld(vdn + 4 * (w + 1)));
+                            nb = fast_bulk<false, MAG>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)),
+                                                       lds_ld(vdn + 4 * (w + 1)));
                             nxt_cache = c2;
                         } else {
                             // first dword of the next row: its upper row is this one (new)
-                            nb = fast_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
-                                                 lds_ld(vnd));
+                            nb = fast_bulk<true, MAG>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4),
+                                                      lds_ld(vcur), lds_ld(vnd));
                         }
                         uint32_t f[4];
 #pragma unroll
@@ -520,16 +552,21 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                     }
                     if (y == L - 1 && l.record != kRecNone) {
                         const uint32_t Rk = acc ? C : R;
-                        const int k = 2 * (int)((Rk - tab0) / 20u);
-                        const int64_t cidx = (int64_t)k * p.C + it.chain0 + lane;
+                        // bin: k (row k/2) or, multimagnetic, the up-spin count m (the row)
+                        const int bin = MAG ? (int)((Rk - tab0) / RB) : 2 * (int)((Rk - tab0) / RB);
+                        const int64_t cidx = (int64_t)bin * p.C + it.chain0 + lane;
                         g_i32 *h = (g_i32 *)p.hist;
                         h[cidx] += 1;
                         if (l.record == kRecProd) {
-                            int ones = 0;
-                            for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
-                            const int m = 2 * ones - L * L;
                             g_i64 *s = (g_i64 *)p.sabs;
-                            s[cidx] += (int64_t)(m < 0 ? -m : m);
+                            if (MAG) {
+                                s[cidx] += (int64_t)lattice_bonds<L>(sb);
+                            } else {
+                                int ones = 0;
+                                for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
+                                const int m = 2 * ones - L * L;
+                                s[cidx] += (int64_t)(m < 0 ? -m : m);
+                            }
                         }
                     }
                 }
@@ -542,7 +579,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     if (active) {
         const uint32_t Rk = acc ? C : R;
-        p.k[it.chain0 + lane] = 2 * (int)((Rk - tab0) / 20u);
+        p.k[it.chain0 + lane] = MAG ? lattice_bonds<L>(sb) : 2 * (int)((Rk - tab0) / RB);
         int ones = 0;
         for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
         p.m[it.chain0 + lane] = 2 * ones - L * L;
@@ -559,14 +596,15 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     }
 }
 
+template <bool MAG>
 __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                       const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
     switch (p.L) {
-    case 16: run_ising_fast<16>(p, it, lds, l, sweep0, plan); return true;
-    case 24: run_ising_fast<24>(p, it, lds, l, sweep0, plan); return true;
-    case 32: run_ising_fast<32>(p, it, lds, l, sweep0, plan); return true;
-    case 48: run_ising_fast<48>(p, it, lds, l, sweep0, plan); return true;
-    case 64: run_ising_fast<64>(p, it, lds, l, sweep0, plan); return true;
+    case 16: run_ising_fast<16, MAG>(p, it, lds, l, sweep0, plan); return true;
+    case 24: run_ising_fast<24, MAG>(p, it, lds, l, sweep0, plan); return true;
+    case 32: run_ising_fast<32, MAG>(p, it, lds, l, sweep0, plan); return true;
+    case 48: run_ising_fast<48, MAG>(p, it, lds, l, sweep0, plan); return true;
+    case 64: run_ising_fast<64, MAG>(p, it, lds, l, sweep0, plan); return true;
     default: return false;
     }
 }
@@ -819,8 +857,8 @@ __device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const 
         for (int j = tid; j < n; j += nthreads) t[j] = p.table[j];
         tab = t;
     }
-    if (MODEL == kIsing && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
-        if (run_fast_if_supported(p, it, lds, l, sweep0, plan)) return;
+    if ((MODEL == kIsing || MODEL == kIsingMag) && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
+        if (run_fast_if_supported<MODEL == kIsingMag>(p, it, lds, l, sweep0, plan)) return;
     }
     if (MODEL == kPotts && SPIN_LDS && TAB_LDS && fast_potts_ok(p, l.n_producer_waves)) {
         if (run_potts_fast_if_supported(p, it, lds, l, sweep0, plan)) return;

@@ -278,19 +278,22 @@ def test_interface_tension_of_a_production_run():
 
 
 MAG_PROBS = [Problem(ISING_MAG, 6, 100, 21, beta=0.66), Problem(ISING_MAG, 16, 40, 22, beta=0.4407),
-             Problem(ISING_MAG, 12, 65, 23, beta=1.1)]
+             Problem(ISING_MAG, 12, 65, 23, beta=1.1), Problem(ISING_MAG, 24, 33, 24, beta=0.66),
+             Problem(ISING_MAG, 32, 20, 25, beta=0.5)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "-".join(f"{k[:4]}{v}" for k, v in c.items()))
 @pytest.mark.parametrize("prob", MAG_PROBS, ids=lambda p: f"mag L{p.L}C{p.n_chains}b{p.beta}")
 def test_multimagnetic_bit_exact(prob, cfg):
     """Multimagnetic Ising (weights over M at fixed beta, Sec. 4) in every
-    launch configuration: spins, k, M, per-chain and merged histograms over m,
-    weights and the two-factor tables equal the oracle's."""
+    launch configuration, the generic walker and the fast one: spins, k, M,
+    per-chain and merged histograms over m, weights and the two-factor tables
+    equal the oracle's."""
     pm = _pm()
     print("case", prob, cfg, flush=True)
     with pm.Muca([prob], **cfg) as ctx:
-        assert ctx.launch_info()["fast_walker"] == 0
+        placed = cfg["rng_mode"] > 1 and cfg["spin_placement"] == 1 and cfg["table_placement"] == 1
+        assert ctx.launch_info()["fast_walker"] == int(placed and prob.L in (16, 24, 32, 48, 64))
         orc = _orc(prob)
         assert ctx.table().shape == (prob.L * prob.L + 1, 10)
         assert np.array_equal(ctx.table(), orc.T)
@@ -323,3 +326,25 @@ def test_multimagnetic_batched_with_energy_models_and_production():
         assert np.array_equal(cnt, ocnt) and np.array_equal(ksum, oks)
         with pytest.raises(pm.MucaError, match="weights over E"):
             ctx.reweight(0, [0.3, 0.4])
+
+
+@pytest.mark.parametrize("L", [16, 48])
+def test_multimagnetic_fast_walker_production(L):
+    """The fast walker's multimagnetic variant: after weight iterations, a
+    production run's counts per m and sums of k per m (k recounted from the
+    LDS lattice each sweep) equal the oracle's, and so do the final k and M."""
+    pm = _pm()
+    prob = Problem(ISING_MAG, L, 40, 26 + L, beta=0.66)
+    with pm.Muca([prob], rng_mode=4, chains_per_wg=16, spin_placement=1, table_placement=1) as ctx:
+        assert ctx.launch_info()["fast_walker"] == 1
+        orc = _orc(prob)
+        for it in range(3):
+            ctx.iterate(100)
+            orc.iterate(100)
+        ctx.sweep(50, pm.REC_NONE)
+        ctx.sweep(120, pm.REC_PROD)
+        orc.sweeps(50, oracle.REC_NONE)
+        cnt, ksum = orc.production(0, 120)
+        assert np.array_equal(ctx.prod_counts(), cnt) and np.array_equal(ctx.prod_absm(), ksum)
+        assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
+        assert np.array_equal(ctx.spins(), orc.spins)

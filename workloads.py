@@ -10,6 +10,7 @@ temperature (random spins) from a seed (Sec. 3, "Systems and Implementation
 Issues").  The shapes below are the workloads the paper studies (2D periodic
 Ising and 8-state Potts, Sec. 3) at the sizes of the measured configurations.
 """
+import math
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
@@ -72,6 +73,12 @@ _C4_SHAPES = [(ISING, 16), (ISING, 24), (ISING, 32), (ISING, 48), (ISING, 64),
 C4 = RunPlan(problems=tuple(Problem(m, L, 512, s + 1, q=(2 if m == ISING else 8))
                             for s, (m, L) in enumerate(_C4_SHAPES)),
              sweeps_per_iter=2_000, n_iters=10)
+
+# Multimagnetic Ising (Sec. 4): weights over the magnetization at beta = (3/2) beta_0,
+# L=32 (the largest size of the paper's multimagnetic runs), 4096 chains, 2e3 sweeps.
+BETA0_ISING = 0.5 * math.log(1.0 + math.sqrt(2.0))
+C_MAG = RunPlan(problems=(Problem(ISING_MAG, 32, 4096, 1, beta=1.5 * BETA0_ISING),), sweeps_per_iter=2_000,
+                n_iters=30)
 
 # Learned initial weights: training sizes and seeded test runs.
 C5_TRAIN: List[Tuple[int, int]] = [(ISING, 8), (ISING, 16), (ISING, 24), (ISING, 32), (ISING, 48),
