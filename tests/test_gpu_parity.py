@@ -183,9 +183,10 @@ def test_production_and_reweighting():
                 assert np.all(np.isnan(m))
 
 
-def test_checkpoint_restore_continues_bit_exact():
+@pytest.mark.parametrize("prob", [Problem(POTTS, 8, 40, 31, q=8), Problem(ISING_MAG, 16, 40, 32, beta=0.66)],
+                         ids=["potts", "mag"])
+def test_checkpoint_restore_continues_bit_exact(prob):
     pm = _pm()
-    prob = Problem(POTTS, 8, 40, 31, q=8)
     with pm.Muca([prob]) as a:
         for _ in range(3):
             a.iterate(200)
@@ -199,6 +200,13 @@ def test_checkpoint_restore_continues_bit_exact():
                 b.iterate(200)
             assert np.array_equal(a.spins(), b.spins()) and _same_bits(a.lnW(), b.lnW())
             assert np.array_equal(a.H(), b.H())
+            assert np.array_equal(a.k(), b.k()) and np.array_equal(a.m(), b.m())
+    # a checkpoint of another beta is refused
+    if prob.model == ISING_MAG:
+        other = Problem(ISING_MAG, prob.L, prob.n_chains, prob.seed, beta=prob.beta + 0.1)
+        with pm.Muca([other]) as c:
+            with pytest.raises(pm.MucaError, match="differs"):
+                c.restore(blob)
 
 
 def test_set_log_weights_canonical_limit():

@@ -61,3 +61,11 @@ def test_library_equal_height_long_tail():
     cnt[lo:hi + tail + 1] = 1
     got = _lib_vs_oracle(POTTS, L, -(B0_POTTS8 * E + f), cnt, B0_POTTS8 - 0.02, B0_POTTS8 + 0.015)
     assert got["sigma"] == pytest.approx(h / L, rel=1e-12)
+
+
+def test_library_equal_height_refuses_the_magnetization_axis():
+    import paper_1212_3975_amd as pm
+    L = 8
+    lnW, cnt = double_well(POTTS, L, 30, 40, 1.0, B0_POTTS8)
+    with pytest.raises(pm.MucaError):
+        pm.equal_height(pm.ISING_MAG, L, lnW, cnt, 1.3, 1.4)
