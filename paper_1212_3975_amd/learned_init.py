@@ -39,6 +39,7 @@ def iterate_to_flat(ctx, sweeps: int, cap: int, label: str, log_every: int = 10,
     or after `max_seconds` of wall time."""
     hist = []
     t0 = time.time()
+    t_log = t0
     for it in range(1, cap + 1):
         if time.time() - t0 > max_seconds:
             print(f"  {label} stopped after {it - 1} iterations ({max_seconds:.0f} s limit)", flush=True)
@@ -46,7 +47,9 @@ def iterate_to_flat(ctx, sweeps: int, cap: int, label: str, log_every: int = 10,
         st = ctx.iterate(sweeps)[0]
         hist.append({"it": it, "visited": st["visited"], "reachable": st["reachable"],
                      "min_over_max": round(st["min_over_max"], 4), "flat": st["flat"]})
-        if it % log_every == 0 or st["flat"]:
+        # a line every log_every iterations, and at least every 30 s on large lattices
+        if it % log_every == 0 or st["flat"] or time.time() - t_log > 30.0:
+            t_log = time.time()
             print(f"  {label} it={it} visited={st['visited']}/{st['reachable']} "
                   f"min/max={st['min_over_max']:.3f} flat={st['flat']} t={time.time() - t0:.1f}s", flush=True)
         if st["flat"]:
@@ -111,7 +114,7 @@ def test(params_path: str, out_dir: str, sizes, chains: int, sweeps: int, cap_pl
                         mlp.set_log_weights(ctx, 0)
                     cap = cap_learned if base == "learned" else cap_plain
                     n_flat, hist = iterate_to_flat(ctx, sweeps, cap, label, log_every=25, max_seconds=max_seconds)
-                iters = n_flat if n_flat else cap
+                iters = n_flat if n_flat else len(hist)   # iterations run (cap or time limit)
                 rec = {"model": NAMES[model], "L": L, "seed": seed, "arm": arm, "chains": chains,
                        "sweeps_per_iter": sweeps, "flat": n_flat is not None, "iterations": iters,
                        "sweeps_per_chain": iters * sweeps, "total_sweeps": iters * sweeps * chains,
