@@ -89,7 +89,17 @@ __host__ __device__ inline int round_up(int v, int a) { return (v + a - 1) / a *
 //          (offset, word, offset, word) per 2 sites and lane
 struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
+    int off_rows;   // packed Ising walker only: the ring of unpacked rows
 };
+// The packed Ising walker (L = 64, more than 16 chains per workgroup): a lane's
+// lattice is 128 dwords of bits (stride 129), its row ring four rows of 16
+// byte dwords (stride 65), and random words come in chunks of half a row.
+constexpr int kPackedBitStride = 129;
+constexpr int kPackedRowStride = 65;
+constexpr int kPackedChunkDwords = 8;
+__host__ __device__ inline bool packed_ising(const ProbDev &p, const WorkItem &it) {
+    return p.model == kIsing && p.L == 64 && it.nchains > 16;
+}
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves);
 __host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves);
 __host__ __device__ constexpr int fast_rows_per_chunk(int L) { return (64 + L - 1) / L; }
@@ -99,6 +109,13 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
     l.off_tab = 0;
     const int tab = p.table_lds ? round_up(p.trows * p.tcols * 4, 16) : 0;
     l.off_spin = l.off_tab + tab;
+    l.off_rows = 0;
+    if (fast_ising_ok(p, n_producer_waves) && packed_ising(p, it)) {
+        l.off_rows = l.off_spin + round_up(it.nchains * kPackedBitStride * 4, 16);
+        l.off_ring = l.off_rows + round_up(it.nchains * kPackedRowStride * 4, 16);
+        l.total = l.off_ring + 2 * it.nchains * (kPackedChunkDwords + 1) * 16;
+        return l;
+    }
     if (fast_ising_ok(p, n_producer_waves)) {
         // lane-major lattice with an odd dword stride; ring [2][lane][chunk dwords + 1] uint4
         const int W = p.L / 4;
@@ -352,6 +369,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) u32x4 lds_u4;
 typedef __attribute__((address_space(1))) int32_t g_i32;
 typedef __attribute__((address_space(1))) int64_t g_i64;
+typedef __attribute__((address_space(1))) uint8_t g_u8;
 
 __device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(const lds_u32 *)(size_t)a; }
 __device__ __forceinline__ void lds_st(uint32_t a, uint32_t v) { *(lds_u32 *)(size_t)a = v; }
@@ -596,9 +614,224 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     }
 }
 
+
+// ------------------------------------------------------------------ packed Ising walker (L = 64)
+//
+// At L = 64 a byte per spin is 4 KB per chain: with the 80 KB table only 16
+// chains fit in LDS, so a walker wave would run with a quarter of its lanes.
+// Here each lattice is kept as bits (bit x of dwords 2y, 2y+1 is site (x, y))
+// and the byte-wise walker above reads a ring of four unpacked rows per lane.
+// While row y is updated, the ring holds row y-1 (already updated), row y
+// (updated in place, a dword at a time) and row y+1 (old), and row y+2 is
+// unpacked into the fourth slot, one dword per updated dword.  The flips are
+// collected as one nibble per dword and xored into the packed row when the row
+// is done.  Rows wrap modulo L, so at row L-2 the already updated row 0 is
+// unpacked for the next sweep.  Random words come in chunks of half a row.
+// The site order, random words and tables are those of the byte walker.
+
+template <int V>
+struct IntConst {
+    static constexpr int value = V;
+};
+
+__device__ __forceinline__ uint32_t spread_nibble(uint32_t n) {
+    // bits 0..3 of n into bits 0, 8, 16, 24 (the partial products never overlap)
+    return __umul24(n, 0x00204081u) & 0x01010101u;
+}
+
+__device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                                   uint32_t sweep0, const LdsPlan &plan) {
+    constexpr int L = 64, W = 16, NB = 128;            // dwords per row (bytes), bit dwords per lattice
+    constexpr int CDW = kPackedChunkDwords, NCH = L * W / CDW;   // chunks per sweep
+    constexpr int PB = kPackedBitStride, PR = kPackedRowStride;
+    constexpr uint32_t RB = 20u;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthreads = blockDim.x;
+    const int nch = it.nchains;
+    const bool active = (wave == 0) && (lane < nch);
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab;
+    const uint32_t bits0 = lbase + (uint32_t)plan.off_spin;
+    const uint32_t rows0 = lbase + (uint32_t)plan.off_rows;
+    const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
+    const uint32_t ringbuf = (uint32_t)nch * (CDW + 1) * 16u;
+
+    // stage the lattice as bits: dword d of lane c holds sites 32d..32d+31
+    for (int j = tid; j < NB * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const g_u8 *g = (const g_u8 *)p.spins + (int64_t)(32 * d) * p.C + it.chain0 + c;
+        uint32_t v = 0;
+        for (int b = 0; b < 32; ++b) v |= (uint32_t)g[(int64_t)b * p.C] << b;
+        lds_st(bits0 + (uint32_t)(c * PB + d) * 4u, v);
+    }
+    __syncthreads();
+
+    const uint32_t bl = bits0 + (uint32_t)(lane * PB) * 4u;   // this lane's bits
+    const uint32_t rl = rows0 + (uint32_t)(lane * PR) * 4u;   // this lane's row ring
+    const uint32_t rb = ring0 + (uint32_t)(lane * (CDW + 1)) * 16u;
+    auto slot = [&](int y) -> uint32_t { return rl + (uint32_t)((y & 3) * W) * 4u; };
+    // byte dword w of row y, unpacked from the bits
+    auto unpacked = [&](int y, int w) -> uint32_t {
+        const uint32_t word = lds_ld(bl + (uint32_t)(2 * y + (w >> 3)) * 4u);
+        return spread_nibble(__builtin_amdgcn_ubfe(word, 4u * (uint32_t)(w & 7), 4u));
+    };
+
+    uint32_t R = 0, C = 0, tA = 0, tB = 0;
+    bool acc = false;
+    FastBulk nb{0, 0, 0, 0, 0};
+    if (active) {
+        // ring: rows L-1, 0, 1 (row 2 is unpacked while row 0 is updated)
+        for (int w = 0; w < W; ++w) {
+            lds_st(slot(L - 1) + 4u * w, unpacked(L - 1, w));
+            lds_st(slot(0) + 4u * w, unpacked(0, w));
+            lds_st(slot(1) + 4u * w, unpacked(1, w));
+        }
+        const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
+        R = tab0 + RB * (uint32_t)(k >> 1);
+        C = R;
+        const uint32_t r0 = slot(0);
+        nb = fast_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(slot(L - 1)),
+                             lds_ld(slot(1)));
+        tA = lds_ld(R + ubyte(nb.a0, 0));
+        tB = tA;
+    }
+
+    // producers: chunk t covers dwords (t mod NCH) * CDW .. + CDW - 1 of sweep t / NCH
+    auto produce = [&](int t) {
+        const int sw = t / NCH;
+        const uint32_t sweep = sweep0 + (uint32_t)sw;
+        const int blk0 = (t - sw * NCH) * CDW;
+        const uint32_t buf = ring0 + (uint32_t)(t & 1) * ringbuf;
+        const int total = CDW * nch;
+        for (int w = tid - 64; w < total; w += nthreads - 64) {
+            const int c = w / CDW, q = w - c * CDW;
+            const uint4 b = philox4x32_10((uint32_t)(blk0 + q), sweep, (uint32_t)(it.chain0 + c), 0u, p.seed_lo,
+                                          p.seed_hi);
+            lds_st4(buf + (uint32_t)(c * (CDW + 1) + q) * 16u,
+                    make_uint4(min(b.x, 0xFFFFFFFEu), min(b.y, 0xFFFFFFFEu), min(b.z, 0xFFFFFFFEu),
+                               min(b.w, 0xFFFFFFFEu)));
+        }
+    };
+
+    const int total_chunks = NCH * l.n_sweeps;   // even: two halves per row
+    if (wave > 0) produce(0);
+    __syncthreads();
+    uint4 u_next = make_uint4(0, 0, 0, 0);
+    uint32_t fl0 = 0, fl1 = 0;   // flips of the current row: sites 0..31, 32..63
+    // One half row; H is a compile-time constant so that every dword index,
+    // LDS offset and flip word below is fixed at compile time.
+    auto walk_half = [&](auto HC, int t) {
+        constexpr int H = decltype(HC)::value;
+        const int y = (t % NCH) >> 1;
+        const uint32_t ub = rb + (uint32_t)(t & 1) * ringbuf;
+        const uint32_t vcur = slot(y), vnc = slot(y + 1), vnd = slot(y + 2), vup = slot(y + 3);
+        const int y2 = (y + 2 == L) ? 0 : (y + 2 == L + 1) ? 1 : y + 2;   // row unpacked into vnd
+        const uint32_t bits_y2 = bl + (uint32_t)(2 * y2 + H) * 4u;        // its half of row y2
+        const uint32_t word_y2 = lds_ld(bits_y2);
+        uint32_t nxt_cache = lds_ld(vcur + 4 * (8 * H + 1));
+#pragma unroll
+        for (int q = 0; q < CDW; ++q) {
+            const int w = 8 * H + q;
+            const FastBulk b = nb;
+            const uint4 u = (q == 0) ? lds_ld4(ub) : u_next;
+            if (q + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(q + 1) * 16u);
+            // row y+2 into the ring (the slot of row y-2, no longer read)
+            lds_st(vnd + 4u * w, spread_nibble(__builtin_amdgcn_ubfe(word_y2, 4u * (uint32_t)q, 4u)));
+            if (w + 1 < W) {
+                const uint32_t c1 = nxt_cache;
+                const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                nb = fast_bulk<false>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)), lds_ld(vnc + 4 * (w + 1)));
+                nxt_cache = c2;
+            } else {
+                nb = fast_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
+                                     lds_ld(vnd));
+            }
+            uint32_t f[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t Rj = acc ? C : R;
+                const int32_t Ej = acc ? sbyte(b.e1, j) : sbyte(b.e0, j);
+                const uint32_t Cj = Rj + (uint32_t)Ej;
+                const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
+                const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
+                const uint32_t nA = lds_ld(Rj + a0);
+                const uint32_t nB = lds_ld(Cj + a1);
+                const uint32_t tj = acc ? tB : tA;
+                const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+                acc = uj < tj;
+                f[j] = acc ? (1u << j) : 0u;   // accepted: flip site j of the dword
+                R = Rj;
+                C = Cj;
+                tA = nA;
+                tB = nB;
+            }
+            const uint32_t nib = f[0] | f[1] | f[2] | f[3];
+            lds_st(vcur + 4 * w, b.cur ^ spread_nibble(nib));
+            if (H == 0) fl0 |= nib << (4 * q);
+            else fl1 |= nib << (4 * q);
+        }
+        if (H == 1) {
+            // row y done: fold its flips into the bits
+            const uint32_t a0 = bl + (uint32_t)(2 * y) * 4u;
+            lds_st(a0, lds_ld(a0) ^ fl0);
+            lds_st(a0 + 4u, lds_ld(a0 + 4u) ^ fl1);
+            fl0 = 0;
+            fl1 = 0;
+            if (y == L - 1 && l.record != kRecNone) {
+                const uint32_t Rk = acc ? C : R;
+                const int k = 2 * (int)((Rk - tab0) / RB);
+                const int64_t cidx = (int64_t)k * p.C + it.chain0 + lane;
+                g_i32 *hh = (g_i32 *)p.hist;
+                hh[cidx] += 1;
+                if (l.record == kRecProd) {
+                    int ones = 0;
+                    for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
+                    const int m = 2 * ones - L * L;
+                    g_i64 *s = (g_i64 *)p.sabs;
+                    s[cidx] += (int64_t)(m < 0 ? -m : m);
+                }
+            }
+        }
+    };
+    for (int t = 0; t < total_chunks; t += 2) {
+        if (wave == 0) {
+            if (active) walk_half(IntConst<0>{}, t);
+        } else {
+            produce(t + 1);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            if (active) walk_half(IntConst<1>{}, t + 1);
+        } else if (t + 2 < total_chunks) {
+            produce(t + 2);
+        }
+        __syncthreads();
+    }
+
+    if (active) {
+        const uint32_t Rk = acc ? C : R;
+        ((g_i32 *)p.k)[it.chain0 + lane] = 2 * (int)((Rk - tab0) / RB);
+        int ones = 0;
+        for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
+        ((g_i32 *)p.m)[it.chain0 + lane] = 2 * ones - L * L;
+    }
+    __syncthreads();
+    // bits back to bytes in HBM
+    for (int j = tid; j < NB * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint32_t v = lds_ld(bits0 + (uint32_t)(c * PB + d) * 4u);
+        g_u8 *g = (g_u8 *)p.spins + (int64_t)(32 * d) * p.C + it.chain0 + c;
+        for (int b = 0; b < 32; ++b) g[(int64_t)b * p.C] = (uint8_t)((v >> b) & 1u);
+    }
+}
+
 template <bool MAG>
 __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                       const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
+    if (!MAG && packed_ising(p, it)) {
+        run_ising_packed64(p, it, lds, l, sweep0, plan);
+        return true;
+    }
     switch (p.L) {
     case 16: run_ising_fast<16, MAG>(p, it, lds, l, sweep0, plan); return true;
     case 24: run_ising_fast<24, MAG>(p, it, lds, l, sweep0, plan); return true;
@@ -842,7 +1075,8 @@ __device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, co
 // ------------------------------------------------------------------ work item driver
 
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
-__device__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l, uint32_t sweep0) {
+__device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                                         uint32_t sweep0) {
     const LdsPlan plan = lds_plan(p, it, l.n_producer_waves);
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;

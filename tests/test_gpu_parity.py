@@ -356,3 +356,25 @@ def test_multimagnetic_fast_walker_production(L):
         assert np.array_equal(ctx.prod_counts(), cnt) and np.array_equal(ctx.prod_absm(), ksum)
         assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
         assert np.array_equal(ctx.spins(), orc.spins)
+
+
+@pytest.mark.parametrize("chains,cw", [(100, 64), (40, 32)], ids=["c100-cw64", "c40-cw32"])
+def test_packed_l64_walker_bit_exact(chains, cw):
+    """Ising L = 64 with more than 16 chains per workgroup keeps the lattice as
+    bits and unpacks a ring of rows (with 32 + 8 chains one launch mixes the
+    packed and the byte layout): trajectories, histograms, weights, and
+    production counts and |M| sums equal the oracle's."""
+    pm = _pm()
+    prob = Problem(ISING, 64, chains, 41 + chains)
+    with pm.Muca([prob], rng_mode=4, chains_per_wg=cw, spin_placement=1, table_placement=1) as ctx:
+        info = ctx.launch_info()
+        print("launch", info, flush=True)
+        assert info["fast_walker"] == 1 and info["chains_per_wg"] == cw
+        orc = _orc(prob)
+        _compare_iterations(ctx, orc, 3, 40)
+        ctx.sweep(20, pm.REC_NONE)
+        ctx.sweep(30, pm.REC_PROD)
+        orc.sweeps(20, oracle.REC_NONE)
+        cnt, sab = orc.production(0, 30)
+        assert np.array_equal(ctx.prod_counts(), cnt) and np.array_equal(ctx.prod_absm(), sab)
+        assert np.array_equal(ctx.spins(), orc.spins)
