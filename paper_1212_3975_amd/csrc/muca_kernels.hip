@@ -163,17 +163,70 @@ bool uses_fast_walker(const ProbDev &p, int n_producer_waves) {
     return fast_ising_ok(p, n_producer_waves) || fast_potts_ok(p, n_producer_waves);
 }
 
+// Every access of the sweep kernel names its address space: LDS through
+// 32-bit LDS addresses, device memory through address_space(1) pointers.
+// Generic (flat) accesses would be slower and, because a flat access may go
+// to either memory, would make the compiler wait for all outstanding LDS reads
+// wherever one of them might still be pending.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u4;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) int64_t g_i64;
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+__device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(const lds_u32 *)(size_t)a; }
+__device__ __forceinline__ void lds_st(uint32_t a, uint32_t v) { *(lds_u32 *)(size_t)a = v; }
+__device__ __forceinline__ uint4 lds_ld4(uint32_t a) {
+    const u32x4 v = *(const lds_u4 *)(size_t)a;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_st4(uint32_t a, uint4 v) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(lds_u4 *)(size_t)a = w;
+}
+
 template <bool LDS>
-struct SpinRef {
-    // LDS: base = lattice + 4 * lane, stride = bytes per dword row (4 * spin_stride)
-    // HBM: base = spins + chain, stride = C
-    uint8_t *base;
+struct SpinRef;
+// Lattice in LDS: base = LDS byte address of the lane's bytes in dword 0, stride
+// = bytes per dword row (4 * spin_stride); site i is byte i & 3 of dword i >> 2.
+template <>
+struct SpinRef<true> {
+    uint32_t base;
     int stride;
-    __device__ __forceinline__ int64_t off(int site) const {
-        return LDS ? (int64_t)(site >> 2) * stride + (site & 3) : (int64_t)site * stride;
+    __device__ __forceinline__ uint32_t addr(int site) const {
+        return base + (uint32_t)((site >> 2) * stride + (site & 3));
     }
-    __device__ __forceinline__ uint8_t ld(int site) const { return base[off(site)]; }
-    __device__ __forceinline__ void st(int site, uint8_t v) const { base[off(site)] = v; }
+    __device__ __forceinline__ uint8_t ld(int site) const { return *(const lds_u8 *)(size_t)addr(site); }
+    __device__ __forceinline__ void st(int site, uint8_t v) const { *(lds_u8 *)(size_t)addr(site) = v; }
+};
+// Lattice in HBM: base = spins + chain, stride = C.
+template <>
+struct SpinRef<false> {
+    g_u8 *base;
+    int64_t stride;
+    __device__ __forceinline__ uint8_t ld(int site) const { return base[(int64_t)site * stride]; }
+    __device__ __forceinline__ void st(int site, uint8_t v) const { base[(int64_t)site * stride] = v; }
+};
+
+// Threshold table in LDS (LDS byte address) or in HBM.
+template <bool LDS>
+struct TabRef;
+template <>
+struct TabRef<true> {
+    uint32_t base;
+    __device__ __forceinline__ uint32_t ld(int idx) const { return lds_ld(base + 4u * (uint32_t)idx); }
+};
+template <>
+struct TabRef<false> {
+    const g_u32 *base;
+    __device__ __forceinline__ uint32_t ld(int idx) const { return base[idx]; }
 };
 
 // Producer waves: stage the random words of chunk `t` (global chunk counter)
@@ -182,7 +235,7 @@ struct SpinRef {
 // "stored < T" means T == 0xffffffff or u < T.  Potts also stores the
 // proposal offset floor(r (q-1) / 2^32).
 template <int MODEL>
-__device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring, int t, int nchunks,
+__device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint32_t ring, int t, int nchunks,
                               uint32_t sweep0, int ptid, int nprod_threads) {
     const int sw = t / nchunks;
     const int chunk = t - sw * nchunks;
@@ -193,7 +246,7 @@ __device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring,
     const int nblk = (i1 - i0 + SPB - 1) / SPB;
     const int total = nblk * it.nchains;
     const int ls = it.spin_stride;
-    uint4 *r = ring + (t & 1) * (kChunkSites / SPB) * ls;
+    const uint32_t r = ring + (uint32_t)((t & 1) * (kChunkSites / SPB) * ls) * 16u;   // LDS byte address
     const uint32_t qm1 = (uint32_t)(p.q - 1);
     for (int w = ptid; w < total; w += nprod_threads) {
         const int b = w / it.nchains;
@@ -208,7 +261,7 @@ __device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint4 *ring,
             o = make_uint4((uint32_t)(((uint64_t)blk.x * qm1) >> 32), min(blk.y, 0xFFFFFFFEu),
                            (uint32_t)(((uint64_t)blk.z * qm1) >> 32), min(blk.w, 0xFFFFFFFEu));
         }
-        r[b * ls + lane] = o;
+        lds_st4(r + (uint32_t)(b * ls + lane) * 16u, o);
     }
 }
 
@@ -222,7 +275,7 @@ struct WalkState {
 
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
 __device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN_LDS> &S,
-                                            const uint32_t *tab, WalkState &st, uint32_t u, uint32_t tq) {
+                                            const TabRef<TAB_LDS> &tab, WalkState &st, uint32_t u, uint32_t tq) {
     const int L = p.L, N = p.N, i = st.i, x = st.x, y = st.y;
     const int il = (x == 0) ? i + L - 1 : i - 1;
     const int ir = (x == L - 1) ? i - L + 1 : i + 1;
@@ -255,7 +308,7 @@ __device__ __forceinline__ void update_site(const ProbDev &p, const SpinRef<SPIN
         drow = after - before;
         col = drow + 4;
     }
-    const uint32_t t = tab[st.row * (MODEL == kIsing ? 5 : MODEL == kIsingMag ? 10 : 9) + col];
+    const uint32_t t = tab.ld(st.row * (MODEL == kIsing ? 5 : MODEL == kIsingMag ? 10 : 9) + col);
     const bool acc = u < t;   // u arrives as min(u, 0xfffffffe)
     if (acc) {
         S.st(i, snew);
@@ -276,7 +329,7 @@ __device__ __forceinline__ uint32_t clampw(uint32_t u) { return min(u, 0xFFFFFFF
 // The generic walker's pass over chunk t.
 template <int MODEL, bool SPIN_LDS, bool TAB_LDS, bool OWN_RNG>
 __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it, const SpinRef<SPIN_LDS> &S,
-                                           const uint32_t *tab, const uint4 *ring, WalkState &st, int t,
+                                           const TabRef<TAB_LDS> &tab, uint32_t ring, WalkState &st, int t,
                                            int nchunks, uint32_t sweep0, int lane, int record) {
     const int sw = t / nchunks;
     const int chunk = t - sw * nchunks;
@@ -313,18 +366,18 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
     } else {
         const int ls = it.spin_stride;
         if (MODEL != kPotts) {
-            const uint4 *r = ring + (t & 1) * (kChunkSites / 4) * ls + lane;
+            const uint32_t r = ring + (uint32_t)((t & 1) * (kChunkSites / 4) * ls + lane) * 16u;
             for (int i = i0; i < i1; i += 4) {
-                const uint4 w = r[((i - i0) >> 2) * ls];
+                const uint4 w = lds_ld4(r + (uint32_t)(((i - i0) >> 2) * ls) * 16u);
                 update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.x, 0u);
                 update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.y, 0u);
                 update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.z, 0u);
                 update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.w, 0u);
             }
         } else {
-            const uint4 *r = ring + (t & 1) * (kChunkSites / 2) * ls + lane;
+            const uint32_t r = ring + (uint32_t)((t & 1) * (kChunkSites / 2) * ls + lane) * 16u;
             for (int i = i0; i < i1; i += 2) {
-                const uint4 w = r[((i - i0) >> 1) * ls];
+                const uint4 w = lds_ld4(r + (uint32_t)(((i - i0) >> 1) * ls) * 16u);
                 update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.y, w.x);
                 if (i + 1 < i1) update_site<MODEL, SPIN_LDS, TAB_LDS>(p, S, tab, st, w.w, w.z);
             }
@@ -335,9 +388,10 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
         // |M| per energy bin, or the bond count k per magnetization bin
         const int b = (MODEL == kIsing) ? 2 * st.row : st.row;
         const int c = it.chain0 + lane;
-        p.hist[(int64_t)b * p.C + c] += 1;
+        ((g_i32 *)p.hist)[(int64_t)b * p.C + c] += 1;
         if (record == kRecProd)
-            p.sabs[(int64_t)b * p.C + c] += (MODEL == kIsingMag) ? (int64_t)st.k : (int64_t)(st.m < 0 ? -st.m : st.m);
+            ((g_i64 *)p.sabs)[(int64_t)b * p.C + c] +=
+                (MODEL == kIsingMag) ? (int64_t)st.k : (int64_t)(st.m < 0 ? -st.m : st.m);
     }
 }
 
@@ -363,28 +417,6 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
 // compile-time constant, so every neighbour read is a fixed offset from one
 // of three row pointers.  The random words of a chunk of rows sit in a ring
 // [buffer][lane][dword] of uint4.
-
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) u32x4 lds_u4;
-typedef __attribute__((address_space(1))) int32_t g_i32;
-typedef __attribute__((address_space(1))) int64_t g_i64;
-typedef __attribute__((address_space(1))) uint8_t g_u8;
-
-__device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(const lds_u32 *)(size_t)a; }
-__device__ __forceinline__ void lds_st(uint32_t a, uint32_t v) { *(lds_u32 *)(size_t)a = v; }
-__device__ __forceinline__ uint4 lds_ld4(uint32_t a) {
-    const u32x4 v = *(const lds_u4 *)(size_t)a;
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void lds_st4(uint32_t a, uint4 v) {
-    u32x4 w;
-    w.x = v.x;
-    w.y = v.y;
-    w.z = v.z;
-    w.w = v.w;
-    *(lds_u4 *)(size_t)a = w;
-}
 
 __device__ __forceinline__ uint32_t ubyte(uint32_t v, int j) { return (v >> (8 * j)) & 0xFFu; }
 __device__ __forceinline__ int32_t sbyte(uint32_t v, int j) { return (int32_t)(int8_t)(uint8_t)(v >> (8 * j)); }
@@ -468,7 +500,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     // stage the lattice: lane c's dword d = sites 4d..4d+3 of chain chain0 + c
     for (int j = tid; j < NW * nch; j += nthreads) {
         const int d = j / nch, c = j - d * nch;
-        const uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        const g_u8 *g = (const g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
         const uint32_t v = (uint32_t)g[0] | ((uint32_t)g[p.C] << 8) | ((uint32_t)g[2 * (int64_t)p.C] << 16) |
                            ((uint32_t)g[3 * (int64_t)p.C] << 24);
         lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
@@ -483,8 +515,9 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     bool acc = false;
     FastBulk nb{0, 0, 0, 0, 0};
     if (active) {
-        const int k = p.k[it.chain0 + lane];
-        R = MAG ? tab0 + RB * (uint32_t)((p.m[it.chain0 + lane] + L * L) / 2) : tab0 + RB * (uint32_t)(k >> 1);
+        const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
+        R = MAG ? tab0 + RB * (uint32_t)((((const g_i32 *)p.m)[it.chain0 + lane] + L * L) / 2)
+                : tab0 + RB * (uint32_t)(k >> 1);
         C = R;
         const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
         nb = fast_bulk<true, MAG>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1));
@@ -597,16 +630,16 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     if (active) {
         const uint32_t Rk = acc ? C : R;
-        p.k[it.chain0 + lane] = MAG ? lattice_bonds<L>(sb) : 2 * (int)((Rk - tab0) / RB);
+        ((g_i32 *)p.k)[it.chain0 + lane] = MAG ? lattice_bonds<L>(sb) : 2 * (int)((Rk - tab0) / RB);
         int ones = 0;
         for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
-        p.m[it.chain0 + lane] = 2 * ones - L * L;
+        ((g_i32 *)p.m)[it.chain0 + lane] = 2 * ones - L * L;
     }
     __syncthreads();
     for (int j = tid; j < NW * nch; j += nthreads) {
         const int d = j / nch, c = j - d * nch;
         const uint32_t v = lds_ld(spin0 + (uint32_t)(c * P + d) * 4u);
-        uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        g_u8 *g = (g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
         g[0] = (uint8_t)v;
         g[p.C] = (uint8_t)(v >> 8);
         g[2 * (int64_t)p.C] = (uint8_t)(v >> 16);
@@ -920,7 +953,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     for (int j = tid; j < NW * nch; j += nthreads) {
         const int d = j / nch, c = j - d * nch;
-        const uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        const g_u8 *g = (const g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
         const uint32_t v = (uint32_t)g[0] | ((uint32_t)g[p.C] << 8) | ((uint32_t)g[2 * (int64_t)p.C] << 16) |
                            ((uint32_t)g[3 * (int64_t)p.C] << 24);
         lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
@@ -965,7 +998,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     uint4 u_next = make_uint4(0, 0, 0, 0);
     PottsBulk nb{0, 0, 0, 0, 0, 0};
     if (active) {
-        const int k = p.k[it.chain0 + lane];
+        const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
         R = tab0 + ROWB * (uint32_t)k;
         C = R;
         const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
@@ -1046,14 +1079,14 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     if (active) {
         const uint32_t Rk = acc ? C : R;
-        p.k[it.chain0 + lane] = (int)((Rk - tab0) / ROWB);
-        p.m[it.chain0 + lane] = 0;
+        ((g_i32 *)p.k)[it.chain0 + lane] = (int)((Rk - tab0) / ROWB);
+        ((g_i32 *)p.m)[it.chain0 + lane] = 0;
     }
     __syncthreads();
     for (int j = tid; j < NW * nch; j += nthreads) {
         const int d = j / nch, c = j - d * nch;
         const uint32_t v = lds_ld(spin0 + (uint32_t)(c * P + d) * 4u);
-        uint8_t *g = p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        g_u8 *g = (g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
         g[0] = (uint8_t)v;
         g[p.C] = (uint8_t)(v >> 8);
         g[2 * (int64_t)p.C] = (uint8_t)(v >> 16);
@@ -1083,13 +1116,15 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     const int lane = tid & 63;
     const int wave = tid >> 6;
 
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
     // stage the table and the lattice
-    const uint32_t *tab = p.table;
-    if (TAB_LDS) {
-        uint32_t *t = reinterpret_cast<uint32_t *>(lds + plan.off_tab);
+    TabRef<TAB_LDS> tab;
+    if constexpr (TAB_LDS) {
+        tab.base = lbase + (uint32_t)plan.off_tab;
         const int n = p.trows * p.tcols;
-        for (int j = tid; j < n; j += nthreads) t[j] = p.table[j];
-        tab = t;
+        for (int j = tid; j < n; j += nthreads) lds_st(tab.base + 4u * (uint32_t)j, ((const g_u32 *)p.table)[j]);
+    } else {
+        tab.base = (const g_u32 *)p.table;
     }
     if ((MODEL == kIsing || MODEL == kIsingMag) && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
         if (run_fast_if_supported<MODEL == kIsingMag>(p, it, lds, l, sweep0, plan)) return;
@@ -1099,20 +1134,21 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     }
     SpinRef<SPIN_LDS> S;
     const int ls = it.spin_stride;
-    if (SPIN_LDS) {
-        uint8_t *sp = reinterpret_cast<uint8_t *>(lds + plan.off_spin);
+    const uint32_t sp = lbase + (uint32_t)plan.off_spin;   // LDS lattice (SPIN_LDS)
+    if constexpr (SPIN_LDS) {
         const int n = p.N * it.nchains;
         for (int j = tid; j < n; j += nthreads) {
             const int site = j / it.nchains, c = j - site * it.nchains;
-            sp[((site >> 2) * ls + c) * 4 + (site & 3)] = p.spins[(int64_t)site * p.C + it.chain0 + c];
+            *(lds_u8 *)(size_t)(sp + (uint32_t)(((site >> 2) * ls + c) * 4 + (site & 3))) =
+                ((const g_u8 *)p.spins)[(int64_t)site * p.C + it.chain0 + c];
         }
-        S.base = sp + 4 * lane;
+        S.base = sp + 4u * (uint32_t)lane;
         S.stride = 4 * ls;
     } else {
-        S.base = p.spins + it.chain0 + lane;
+        S.base = (g_u8 *)p.spins + it.chain0 + lane;
         S.stride = p.C;
     }
-    uint4 *ring = reinterpret_cast<uint4 *>(lds + plan.off_ring);
+    const uint32_t ring = lbase + (uint32_t)plan.off_ring;
 
     {
         const int nchunks = (p.N + kChunkSites - 1) / kChunkSites;
@@ -1124,8 +1160,8 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
         st.k = 0;
         st.x = st.y = st.i = 0;
         if (active) {
-            const int k = p.k[it.chain0 + lane];
-            st.m = p.m[it.chain0 + lane];
+            const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
+            st.m = ((const g_i32 *)p.m)[it.chain0 + lane];
             st.k = k;
             st.row = (MODEL == kIsing) ? (k >> 1) : (MODEL == kIsingMag) ? (st.m + p.N) / 2 : k;
         }
@@ -1152,17 +1188,17 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
             }
         }
         if (active) {
-            p.k[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : (MODEL == kIsingMag) ? st.k : st.row;
-            p.m[it.chain0 + lane] = st.m;
+            ((g_i32 *)p.k)[it.chain0 + lane] = (MODEL == kIsing) ? 2 * st.row : (MODEL == kIsingMag) ? st.k : st.row;
+            ((g_i32 *)p.m)[it.chain0 + lane] = st.m;
         }
     }
-    if (SPIN_LDS) {
+    if constexpr (SPIN_LDS) {
         __syncthreads();
-        const uint8_t *sp = reinterpret_cast<const uint8_t *>(lds + plan.off_spin);
         const int n = p.N * it.nchains;
         for (int j = tid; j < n; j += nthreads) {
             const int site = j / it.nchains, c = j - site * it.nchains;
-            p.spins[(int64_t)site * p.C + it.chain0 + c] = sp[((site >> 2) * ls + c) * 4 + (site & 3)];
+            ((g_u8 *)p.spins)[(int64_t)site * p.C + it.chain0 + c] =
+                *(const lds_u8 *)(size_t)(sp + (uint32_t)(((site >> 2) * ls + c) * 4 + (site & 3)));
         }
     }
 }
