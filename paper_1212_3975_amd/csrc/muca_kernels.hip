@@ -427,36 +427,128 @@ struct FastBulk {
     uint32_t e0, e1;   // bytes (int8): row byte step 40 - 20D for D0 / D1 (multimagnetic: +-40)
 };
 
-template <bool ROW_START, bool MAG = false>
-__device__ __forceinline__ FastBulk fast_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn) {
+// The bulk of a dword in three pieces (so that a walker can spread it over
+// the sites of the previous dword): the neighbour sums, the candidate counts
+// D0 (left neighbour kept) and D1 (left neighbour flipped), and the byte maps.
+struct BulkSums {
+    uint32_t cur, s3, ml;   // old spins; up+down+right disagreements; left disagreement
+};
+
+__device__ __forceinline__ BulkSums bulk_sums(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn) {
     // right neighbours: bytes cur1 cur2 cur3 nxt0; left (old): prv3 cur0 cur1 cur2
     const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
     const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);
-    const uint32_t s3 = (cur ^ up) + (cur ^ dn) + (cur ^ rn);
-    const uint32_t ml = cur ^ lo;
-    const uint32_t d0 = s3 + ml;
-    uint32_t d1 = s3 + (ml ^ 0x01010101u);
+    return BulkSums{cur, (cur ^ up) + (cur ^ dn) + (cur ^ rn), cur ^ lo};
+}
+
+struct BulkDiff {
+    uint32_t cur, d0, d1;
+};
+
+template <bool ROW_START>
+__device__ __forceinline__ BulkDiff bulk_diff(const BulkSums &q) {
+    BulkDiff d;
+    d.cur = q.cur;
+    d.d0 = q.s3 + q.ml;
+    d.d1 = q.s3 + (q.ml ^ 0x01010101u);
     // the first site of a row has its left neighbour at the row's end, which
     // this sweep has not visited yet: both candidates agree
-    if (ROW_START) d1 = (d1 & 0xFFFFFF00u) | (d0 & 0xFFu);
-    FastBulk b;
-    b.cur = cur;
-    b.a0 = __builtin_amdgcn_perm(0u, 0x04080C10u, d0);           // 16,12,8,4,0
-    b.a1 = __builtin_amdgcn_perm(0u, 0x04080C10u, d1);
+    if (ROW_START) d.d1 = (d.d1 & 0xFFFFFF00u) | (d.d0 & 0xFFu);
+    return d;
+}
+
+// Column byte offsets (16 - 4D) of both candidates.
+template <bool MAG>
+__device__ __forceinline__ void bulk_cols(const BulkDiff &d, FastBulk &b) {
+    b.cur = d.cur;
+    b.a0 = __builtin_amdgcn_perm(0u, 0x04080C10u, d.d0);           // 16,12,8,4,0
+    b.a1 = __builtin_amdgcn_perm(0u, 0x04080C10u, d.d1);
     if (MAG) {
-        // multimagnetic rows are up-spin counts of 40 bytes (ten columns): the
-        // row moves by -40 for an up spin and +40 for a down one, whatever the
-        // left neighbour did, and an up spin reads the columns 5..9
-        const uint32_t s20 = __builtin_amdgcn_perm(0u, 0x00001400u, cur);   // 0 / 20 per byte
+        // multimagnetic rows are up-spin counts of 40 bytes (ten columns): an
+        // up spin reads the columns 5..9
+        const uint32_t s20 = __builtin_amdgcn_perm(0u, 0x00001400u, d.cur);   // 0 / 20 per byte
         b.a0 += s20;
         b.a1 += s20;
-        b.e0 = __builtin_amdgcn_perm(0u, 0x0000D828u, cur);                 // +40 / -40
+    }
+}
+
+// Row byte steps (40 - 20D) of both candidates; multimagnetic rows move by
+// -40 for an up spin and +40 for a down one, whatever the left neighbour did.
+template <bool MAG>
+__device__ __forceinline__ void bulk_steps(const BulkDiff &d, FastBulk &b) {
+    if (MAG) {
+        b.e0 = __builtin_amdgcn_perm(0u, 0x0000D828u, d.cur);                 // +40 / -40
         b.e1 = b.e0;
     } else {
-        b.e0 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d0);        // 40,20,0,-20,-40
-        b.e1 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d1);
+        b.e0 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d.d0);        // 40,20,0,-20,-40
+        b.e1 = __builtin_amdgcn_perm(0xD8u, 0xEC001428u, d.d1);
     }
+}
+
+template <bool ROW_START, bool MAG = false>
+__device__ __forceinline__ FastBulk fast_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn) {
+    const BulkDiff d = bulk_diff<ROW_START>(bulk_sums(cur, prv, nxt, up, dn));
+    FastBulk b;
+    bulk_cols<MAG>(d, b);
+    bulk_steps<MAG>(d, b);
     return b;
+}
+
+// Walker state between sites: the table row before the previous site's move
+// (R) and after it (C), the current site's table words for both outcomes of
+// the previous site (tA kept, tB flipped), and that outcome (acc).
+struct FastState {
+    uint32_t R, C, tA, tB;
+    bool acc;
+};
+
+// The four sites of one dword.  Each site is issued in fenced parts:
+//   1. from the previous site's outcome, the row and the two table reads of
+//      the next site (both outcomes of this one);
+//   2. this site's decision, on the words read one site earlier;
+//   3. independent work: a piece of the next dword's bulk;
+//   4. the flip record of this site.
+// The fences keep about a site of work between a table read and its use,
+// which hides the LDS latency, and keep three or more instructions between a
+// decision and the next read of it as a lane mask, which hides the latency
+// of a compare result.  Pieces: work(0) loads, work(1) neighbour sums,
+// work(2) candidate counts and column maps (site 3's reads need them),
+// work(3) row steps.  Returns the accepted sites of the dword: FLIP << (STRIDE j)
+// for an accepted site j.
+// Row byte step of site j of a dword if it is accepted, for both outcomes of
+// the previous site (Ising and multimagnetic: the step itself; Potts: dk
+// rows of 36 bytes).
+__device__ __forceinline__ int32_t row_step(const FastBulk &b, bool left_flipped, int j) {
+    return left_flipped ? sbyte(b.e1, j) : sbyte(b.e0, j);
+}
+
+template <class Bulk, uint32_t FLIP, int STRIDE, class Work>
+__device__ __forceinline__ uint32_t walk_dword(FastState &s, const Bulk &b, const Bulk &nb, const uint4 &u,
+                                               Work &&work) {
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t Rj = s.acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)row_step(b, s.acc, j);
+        const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
+        const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
+        const uint32_t nA = lds_ld(Rj + a0);
+        const uint32_t nB = lds_ld(Cj + a1);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t tj = s.acc ? s.tB : s.tA;
+        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+        s.acc = uj < tj;
+        s.R = Rj;
+        s.C = Cj;
+        s.tA = nA;
+        s.tB = nB;
+        __builtin_amdgcn_sched_barrier(0);
+        work(j);
+        __builtin_amdgcn_sched_barrier(0);
+        f |= s.acc ? (FLIP << (STRIDE * j)) : 0u;   // accepted: site j
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return f;
 }
 
 // Bond count k of a lane-major LDS lattice (right and down bond of every site).
@@ -511,18 +603,17 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     const uint32_t rb = ring0 + (uint32_t)(lane * (CDW + 1)) * 16u;
     auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
 
-    uint32_t R = 0, C = 0, tA = 0, tB = 0;
-    bool acc = false;
+    FastState st{0, 0, 0, 0, false};
     FastBulk nb{0, 0, 0, 0, 0};
     if (active) {
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
-        R = MAG ? tab0 + RB * (uint32_t)((((const g_i32 *)p.m)[it.chain0 + lane] + L * L) / 2)
-                : tab0 + RB * (uint32_t)(k >> 1);
-        C = R;
+        st.R = MAG ? tab0 + RB * (uint32_t)((((const g_i32 *)p.m)[it.chain0 + lane] + L * L) / 2)
+                   : tab0 + RB * (uint32_t)(k >> 1);
+        st.C = st.R;
         const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
         nb = fast_bulk<true, MAG>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1));
-        tA = lds_ld(R + ubyte(nb.a0, 0));
-        tB = tA;
+        st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
+        st.tB = st.tA;
     }
 
     // producers: chunk t covers rows (t mod NCH) * RPC .. + RPC - 1 of sweep t / NCH
@@ -567,42 +658,42 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                         const FastBulk b = nb;
                         // random words of this dword (prefetched one dword ahead inside the chunk)
                         const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
-                        if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
-                        // bulk of the next dword
-                        if (w + 1 < W) {
-                            const uint32_t c1 = nxt_cache;   // old dword w+1
-                            const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
-                            nb = fast_bulk<false, MAG>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)),
-                                                       lds_ld(vdn + 4 * (w + 1)));
-                            nxt_cache = c2;
-                        } else {
-                            // first dword of the next row: its upper row is this one (new)
-                            nb = fast_bulk<true, MAG>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4),
-                                                      lds_ld(vcur), lds_ld(vnd));
-                        }
-                        uint32_t f[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const uint32_t Rj = acc ? C : R;
-                            const int32_t Ej = acc ? sbyte(b.e1, j) : sbyte(b.e0, j);
-                            const uint32_t Cj = Rj + (uint32_t)Ej;
-                            const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
-                            const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
-                            const uint32_t nA = lds_ld(Rj + a0);
-                            const uint32_t nB = lds_ld(Cj + a1);
-                            const uint32_t tj = acc ? tB : tA;
-                            const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
-                            acc = uj < tj;
-                            f[j] = acc ? (1u << (8 * j)) : 0u;   // accepted: flip byte j
-                            R = Rj;
-                            C = Cj;
-                            tA = nA;
-                            tB = nB;
-                        }
-                        lds_st(vcur + 4 * w, b.cur ^ (f[0] | f[1] | f[2] | f[3]));
+                        // the next dword's bulk, in pieces between this dword's sites
+                        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;
+                        BulkSums ns{0, 0, 0};
+                        BulkDiff nd{0, 0, 0};
+                        auto work = [&](int j) {
+                            if (j == 0) {
+                                if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
+                                if (w + 1 < W) {
+                                    q0 = nxt_cache;                                        // old dword w+1
+                                    q1 = b.cur;
+                                    q2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                                    q3 = lds_ld(vup + 4 * (w + 1));
+                                    q4 = lds_ld(vdn + 4 * (w + 1));
+                                } else {
+                                    // first dword of the next row: its upper row is this one (new)
+                                    q0 = lds_ld(vnc);
+                                    q1 = lds_ld(vnc + 4 * (W - 1));
+                                    q2 = lds_ld(vnc + 4);
+                                    q3 = lds_ld(vcur);
+                                    q4 = lds_ld(vnd);
+                                }
+                            } else if (j == 1) {
+                                ns = bulk_sums(q0, q1, q2, q3, q4);
+                                if (w + 1 < W) nxt_cache = q2;
+                            } else if (j == 2) {
+                                nd = (w + 1 < W) ? bulk_diff<false>(ns) : bulk_diff<true>(ns);
+                                bulk_cols<MAG>(nd, nb);
+                            } else {
+                                bulk_steps<MAG>(nd, nb);
+                            }
+                        };
+                        const uint32_t f = walk_dword<FastBulk, 1u, 8>(st, b, nb, u, work);
+                        lds_st(vcur + 4 * w, b.cur ^ f);
                     }
                     if (y == L - 1 && l.record != kRecNone) {
-                        const uint32_t Rk = acc ? C : R;
+                        const uint32_t Rk = st.acc ? st.C : st.R;
                         // bin: k (row k/2) or, multimagnetic, the up-spin count m (the row)
                         const int bin = MAG ? (int)((Rk - tab0) / RB) : 2 * (int)((Rk - tab0) / RB);
                         const int64_t cidx = (int64_t)bin * p.C + it.chain0 + lane;
@@ -629,7 +720,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     }
 
     if (active) {
-        const uint32_t Rk = acc ? C : R;
+        const uint32_t Rk = st.acc ? st.C : st.R;
         ((g_i32 *)p.k)[it.chain0 + lane] = MAG ? lattice_bonds<L>(sb) : 2 * (int)((Rk - tab0) / RB);
         int ones = 0;
         for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
@@ -709,8 +800,7 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
         return spread_nibble(__builtin_amdgcn_ubfe(word, 4u * (uint32_t)(w & 7), 4u));
     };
 
-    uint32_t R = 0, C = 0, tA = 0, tB = 0;
-    bool acc = false;
+    FastState st{0, 0, 0, 0, false};
     FastBulk nb{0, 0, 0, 0, 0};
     if (active) {
         // ring: rows L-1, 0, 1 (row 2 is unpacked while row 0 is updated)
@@ -720,13 +810,13 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
             lds_st(slot(1) + 4u * w, unpacked(1, w));
         }
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
-        R = tab0 + RB * (uint32_t)(k >> 1);
-        C = R;
+        st.R = tab0 + RB * (uint32_t)(k >> 1);
+        st.C = st.R;
         const uint32_t r0 = slot(0);
         nb = fast_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(slot(L - 1)),
                              lds_ld(slot(1)));
-        tA = lds_ld(R + ubyte(nb.a0, 0));
-        tB = tA;
+        st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
+        st.tB = st.tA;
     }
 
     // producers: chunk t covers dwords (t mod NCH) * CDW .. + CDW - 1 of sweep t / NCH
@@ -767,38 +857,40 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
             const int w = 8 * H + q;
             const FastBulk b = nb;
             const uint4 u = (q == 0) ? lds_ld4(ub) : u_next;
-            if (q + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(q + 1) * 16u);
-            // row y+2 into the ring (the slot of row y-2, no longer read)
-            lds_st(vnd + 4u * w, spread_nibble(__builtin_amdgcn_ubfe(word_y2, 4u * (uint32_t)q, 4u)));
-            if (w + 1 < W) {
-                const uint32_t c1 = nxt_cache;
-                const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
-                nb = fast_bulk<false>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)), lds_ld(vnc + 4 * (w + 1)));
-                nxt_cache = c2;
-            } else {
-                nb = fast_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
-                                     lds_ld(vnd));
-            }
-            uint32_t f[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t Rj = acc ? C : R;
-                const int32_t Ej = acc ? sbyte(b.e1, j) : sbyte(b.e0, j);
-                const uint32_t Cj = Rj + (uint32_t)Ej;
-                const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
-                const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
-                const uint32_t nA = lds_ld(Rj + a0);
-                const uint32_t nB = lds_ld(Cj + a1);
-                const uint32_t tj = acc ? tB : tA;
-                const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
-                acc = uj < tj;
-                f[j] = acc ? (1u << j) : 0u;   // accepted: flip site j of the dword
-                R = Rj;
-                C = Cj;
-                tA = nA;
-                tB = nB;
-            }
-            const uint32_t nib = f[0] | f[1] | f[2] | f[3];
+            // the next dword's bulk (and one dword of row y+2 into the ring),
+            // in pieces between this dword's sites
+            uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;
+            BulkSums ns{0, 0, 0};
+            BulkDiff nd{0, 0, 0};
+            auto work = [&](int j) {
+                if (j == 0) {
+                    if (q + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(q + 1) * 16u);
+                    if (w + 1 < W) {
+                        q0 = nxt_cache;
+                        q1 = b.cur;
+                        q2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                        q3 = lds_ld(vup + 4 * (w + 1));
+                        q4 = lds_ld(vnc + 4 * (w + 1));
+                    } else {
+                        q0 = lds_ld(vnc);
+                        q1 = lds_ld(vnc + 4 * (W - 1));
+                        q2 = lds_ld(vnc + 4);
+                        q3 = lds_ld(vcur);
+                        q4 = lds_ld(vnd);
+                    }
+                } else if (j == 1) {
+                    ns = bulk_sums(q0, q1, q2, q3, q4);
+                    if (w + 1 < W) nxt_cache = q2;
+                } else if (j == 2) {
+                    nd = (w + 1 < W) ? bulk_diff<false>(ns) : bulk_diff<true>(ns);
+                    bulk_cols<false>(nd, nb);
+                } else {
+                    bulk_steps<false>(nd, nb);
+                    // row y+2 into the ring (the slot of row y-2, no longer read)
+                    lds_st(vnd + 4u * w, spread_nibble(__builtin_amdgcn_ubfe(word_y2, 4u * (uint32_t)q, 4u)));
+                }
+            };
+            const uint32_t nib = walk_dword<FastBulk, 1u, 1>(st, b, nb, u, work);
             lds_st(vcur + 4 * w, b.cur ^ spread_nibble(nib));
             if (H == 0) fl0 |= nib << (4 * q);
             else fl1 |= nib << (4 * q);
@@ -811,7 +903,7 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
             fl0 = 0;
             fl1 = 0;
             if (y == L - 1 && l.record != kRecNone) {
-                const uint32_t Rk = acc ? C : R;
+                const uint32_t Rk = st.acc ? st.C : st.R;
                 const int k = 2 * (int)((Rk - tab0) / RB);
                 const int64_t cidx = (int64_t)k * p.C + it.chain0 + lane;
                 g_i32 *hh = (g_i32 *)p.hist;
@@ -842,7 +934,7 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
     }
 
     if (active) {
-        const uint32_t Rk = acc ? C : R;
+        const uint32_t Rk = st.acc ? st.C : st.R;
         ((g_i32 *)p.k)[it.chain0 + lane] = 2 * (int)((Rk - tab0) / RB);
         int ones = 0;
         for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
@@ -900,32 +992,64 @@ __device__ __forceinline__ uint32_t eq8(uint32_t a, uint32_t b) {
     return __builtin_amdgcn_perm(0u, 0x00000001u, a ^ b);
 }
 
+// The Potts bulk in three pieces: proposals and neighbour equalities; the
+// biased differences and column offsets; the row steps.
+struct PottsSums {
+    uint32_t cur, sp;          // old states, proposals
+    uint32_t X0, Y0, X1, Y1;   // equalities with s and with s', left neighbour old (0) or proposed (1)
+};
+
+__device__ __forceinline__ PottsSums potts_sums(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn,
+                                                uint32_t tq4, uint32_t sp_prv) {
+    PottsSums q;
+    q.cur = cur;
+    q.sp = (cur + 0x01010101u + tq4) & 0x07070707u;
+    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
+    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);        // left, old state
+    const uint32_t ln = __builtin_amdgcn_alignbyte(q.sp, sp_prv, 3);    // left, its proposal
+    const uint32_t P = eq8(up, cur) + eq8(dn, cur) + eq8(rn, cur);
+    const uint32_t Q = eq8(up, q.sp) + eq8(dn, q.sp) + eq8(rn, q.sp);
+    q.X0 = P + eq8(lo, cur);
+    q.Y0 = Q + eq8(lo, q.sp);
+    q.X1 = P + eq8(ln, cur);
+    q.Y1 = Q + eq8(ln, q.sp);
+    return q;
+}
+
+// Fills cur, sp, a0, a1 and returns the biased differences (0x80 + dk per byte).
+template <bool ROW_START>
+__device__ __forceinline__ uint2 potts_cols(const PottsSums &q, PottsBulk &b) {
+    uint32_t X1 = q.X1, Y1 = q.Y1;
+    if (ROW_START) {
+        // the first site's left neighbour (row end) has not been visited yet
+        X1 = (X1 & 0xFFFFFF00u) | (q.X0 & 0xFFu);
+        Y1 = (Y1 & 0xFFFFFF00u) | (q.Y0 & 0xFFu);
+    }
+    // dk = X - Y in [-4, 4]: biased bytes 0x80 + dk never borrow
+    const uint32_t b0 = (q.X0 | 0x80808080u) - q.Y0, b1 = (X1 | 0x80808080u) - Y1;
+    b.cur = q.cur;
+    b.sp = q.sp;
+    // column offset 4 (dk + 4) = 4 ((0x80 + dk) - 0x7c)
+    b.a0 = (b0 - 0x7C7C7C7Cu) << 2;
+    b.a1 = (b1 - 0x7C7C7C7Cu) << 2;
+    return make_uint2(b0, b1);
+}
+
+__device__ __forceinline__ void potts_steps(uint2 bd, PottsBulk &b) {
+    b.k0 = bd.x ^ 0x80808080u;
+    b.k1 = bd.y ^ 0x80808080u;
+}
+
 template <bool ROW_START>
 __device__ __forceinline__ PottsBulk potts_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn,
                                                 uint32_t tq4, uint32_t sp_prv) {
     PottsBulk b;
-    b.cur = cur;
-    b.sp = (cur + 0x01010101u + tq4) & 0x07070707u;
-    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
-    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);        // left, old state
-    const uint32_t ln = __builtin_amdgcn_alignbyte(b.sp, sp_prv, 3);    // left, its proposal
-    const uint32_t P = eq8(up, cur) + eq8(dn, cur) + eq8(rn, cur);
-    const uint32_t Q = eq8(up, b.sp) + eq8(dn, b.sp) + eq8(rn, b.sp);
-    const uint32_t X0 = P + eq8(lo, cur), Y0 = Q + eq8(lo, b.sp);
-    uint32_t X1 = P + eq8(ln, cur), Y1 = Q + eq8(ln, b.sp);
-    if (ROW_START) {
-        // the first site's left neighbour (row end) has not been visited yet
-        X1 = (X1 & 0xFFFFFF00u) | (X0 & 0xFFu);
-        Y1 = (Y1 & 0xFFFFFF00u) | (Y0 & 0xFFu);
-    }
-    // dk = X - Y in [-4, 4]: biased bytes 0x80 + dk never borrow
-    const uint32_t b0 = (X0 | 0x80808080u) - Y0, b1 = (X1 | 0x80808080u) - Y1;
-    b.k0 = b0 ^ 0x80808080u;
-    b.k1 = b1 ^ 0x80808080u;
-    // column offset 4 (dk + 4) = 4 ((0x80 + dk) - 0x7c)
-    b.a0 = (b0 - 0x7C7C7C7Cu) << 2;
-    b.a1 = (b1 - 0x7C7C7C7Cu) << 2;
+    potts_steps(potts_cols<ROW_START>(potts_sums(cur, prv, nxt, up, dn, tq4, sp_prv), b), b);
     return b;
+}
+
+__device__ __forceinline__ int32_t row_step(const PottsBulk &b, bool left_flipped, int j) {
+    return 36 * (left_flipped ? sbyte(b.k1, j) : sbyte(b.k0, j));
 }
 
 template <int L>
@@ -993,19 +1117,18 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     const uint32_t rbt = ringt0 + (uint32_t)(lane * (CDW + 1)) * 4u;
     auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
 
-    uint32_t R = 0, C = 0, tA = 0, tB = 0;
-    bool acc = false;
+    FastState st{0, 0, 0, 0, false};
     uint4 u_next = make_uint4(0, 0, 0, 0);
     PottsBulk nb{0, 0, 0, 0, 0, 0};
     if (active) {
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
-        R = tab0 + ROWB * (uint32_t)k;
-        C = R;
+        st.R = tab0 + ROWB * (uint32_t)k;
+        st.C = st.R;
         const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
         nb = potts_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1),
                               lds_ld(rbt), 0u);
-        tA = lds_ld(R + ubyte(nb.a0, 0));
-        tB = tA;
+        st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
+        st.tB = st.tA;
     }
 
     for (int t = 0; t < total_chunks; ++t) {
@@ -1028,43 +1151,43 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const PottsBulk b = nb;
-                        if (w + 1 < W) {
-                            const uint32_t c1 = nxt_cache;
-                            const uint32_t c2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
-                            nb = potts_bulk<false>(c1, b.cur, c2, lds_ld(vup + 4 * (w + 1)), lds_ld(vdn + 4 * (w + 1)),
-                                                   lds_ld(tb + (uint32_t)(r * W + w + 1) * 4u), b.sp);
-                            nxt_cache = c2;
-                        } else {
-                            const uint32_t tq = (r + 1 < RPC) ? lds_ld(tb + (uint32_t)((r + 1) * W) * 4u) : lds_ld(tbn);
-                            nb = potts_bulk<true>(lds_ld(vnc), lds_ld(vnc + 4 * (W - 1)), lds_ld(vnc + 4), lds_ld(vcur),
-                                                  lds_ld(vnd), tq, 0u);
-                        }
                         const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
-                        if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
-                        uint32_t f[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const uint32_t Rj = acc ? C : R;
-                            const int32_t dk = acc ? sbyte(b.k1, j) : sbyte(b.k0, j);
-                            const uint32_t Cj = (uint32_t)((int32_t)Rj + (int32_t)ROWB * dk);
-                            const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
-                            const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
-                            const uint32_t nA = lds_ld(Rj + a0);
-                            const uint32_t nB = lds_ld(Cj + a1);
-                            const uint32_t tj = acc ? tB : tA;
-                            const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
-                            acc = uj < tj;
-                            f[j] = acc ? (0xFFu << (8 * j)) : 0u;   // accepted: take the proposal's byte
-                            R = Rj;
-                            C = Cj;
-                            tA = nA;
-                            tB = nB;
-                        }
-                        const uint32_t mask = f[0] | f[1] | f[2] | f[3];
+                        // the next dword's bulk, in pieces between this dword's sites
+                        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
+                        PottsSums ns{0, 0, 0, 0, 0, 0};
+                        uint2 bd = make_uint2(0, 0);
+                        auto work = [&](int j) {
+                            if (j == 0) {
+                                if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
+                                if (w + 1 < W) {
+                                    q0 = nxt_cache;
+                                    q1 = b.cur;
+                                    q2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                                    q3 = lds_ld(vup + 4 * (w + 1));
+                                    q4 = lds_ld(vdn + 4 * (w + 1));
+                                    q5 = lds_ld(tb + (uint32_t)(r * W + w + 1) * 4u);
+                                } else {
+                                    q0 = lds_ld(vnc);
+                                    q1 = lds_ld(vnc + 4 * (W - 1));
+                                    q2 = lds_ld(vnc + 4);
+                                    q3 = lds_ld(vcur);
+                                    q4 = lds_ld(vnd);
+                                    q5 = (r + 1 < RPC) ? lds_ld(tb + (uint32_t)((r + 1) * W) * 4u) : lds_ld(tbn);
+                                }
+                            } else if (j == 1) {
+                                ns = potts_sums(q0, q1, q2, q3, q4, q5, (w + 1 < W) ? b.sp : 0u);
+                                if (w + 1 < W) nxt_cache = q2;
+                            } else if (j == 2) {
+                                bd = (w + 1 < W) ? potts_cols<false>(ns, nb) : potts_cols<true>(ns, nb);
+                            } else {
+                                potts_steps(bd, nb);
+                            }
+                        };
+                        const uint32_t mask = walk_dword<PottsBulk, 0xFFu, 8>(st, b, nb, u, work);
                         lds_st(vcur + 4 * w, (mask & b.sp) | (~mask & b.cur));
                     }
                     if (y == L - 1 && l.record != kRecNone) {
-                        const uint32_t Rk = acc ? C : R;
+                        const uint32_t Rk = st.acc ? st.C : st.R;
                         const int k = (int)((Rk - tab0) / ROWB);
                         g_i32 *h = (g_i32 *)p.hist;
                         h[(int64_t)k * p.C + it.chain0 + lane] += 1;
@@ -1078,7 +1201,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     }
 
     if (active) {
-        const uint32_t Rk = acc ? C : R;
+        const uint32_t Rk = st.acc ? st.C : st.R;
         ((g_i32 *)p.k)[it.chain0 + lane] = (int)((Rk - tab0) / ROWB);
         ((g_i32 *)p.m)[it.chain0 + lane] = 0;
     }
