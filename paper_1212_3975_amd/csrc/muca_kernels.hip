@@ -126,11 +126,11 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
     }
     if (fast_potts_ok(p, n_producer_waves)) {
         // lane-major lattice; ring of three buffers: [3][lane][chunk dwords + 1] uint4 words
-        // followed by [3][lane][chunk dwords + 1] packed proposal offsets
+        // followed by [3][lane][chunk dwords + 1] uint4 lattice terms
         const int W = p.L / 4;
         const int cdw = fast_rows_per_chunk(p.L) * W;
         l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
-        l.total = l.off_ring + 3 * it.nchains * (cdw + 1) * 20;
+        l.total = l.off_ring + 3 * it.nchains * (cdw + 1) * 32;
         return l;
     }
     const int spn = p.spin_lds ? round_up((p.N + 3) / 4 * it.spin_stride * 4, 16) : 0;
@@ -979,6 +979,17 @@ __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const Wo
 // column byte offset 16 + 4 dk.  Proposal offsets are needed one dword ahead
 // of the walker, across chunk boundaries, so the ring has three buffers and
 // the producers run two chunks ahead.
+//
+// Two chunks ahead, the rows of a chunk and the row below it hold their
+// final values of the previous sweep (or, below the last row, row 0 of this
+// sweep), so the producers also form every term that does not involve the
+// row above (which the walker is updating): with the proposals, the biased
+// counts 0x80 + X - Y of both candidates without the up terms, and for the
+// left neighbour's proposal of a dword's first site (drawn in the previous
+// dword) a bit mask of the values equal to the site's state and to its
+// proposal.  The walker adds the up terms, that first-site term, and at a
+// row's last site the right neighbour, which is the row's first site of this
+// sweep.
 
 struct PottsBulk {
     uint32_t cur;      // old states
@@ -1016,6 +1027,13 @@ __device__ __forceinline__ PottsSums potts_sums(uint32_t cur, uint32_t prv, uint
     return q;
 }
 
+// Column byte offsets 4 (dk + 4) = 4 ((0x80 + dk) - 0x7c) of both candidates
+// from the biased differences.
+__device__ __forceinline__ void potts_maps_a(uint2 bd, PottsBulk &b) {
+    b.a0 = (bd.x - 0x7C7C7C7Cu) << 2;
+    b.a1 = (bd.y - 0x7C7C7C7Cu) << 2;
+}
+
 // Fills cur, sp, a0, a1 and returns the biased differences (0x80 + dk per byte).
 template <bool ROW_START>
 __device__ __forceinline__ uint2 potts_cols(const PottsSums &q, PottsBulk &b) {
@@ -1029,9 +1047,7 @@ __device__ __forceinline__ uint2 potts_cols(const PottsSums &q, PottsBulk &b) {
     const uint32_t b0 = (q.X0 | 0x80808080u) - q.Y0, b1 = (X1 | 0x80808080u) - Y1;
     b.cur = q.cur;
     b.sp = q.sp;
-    // column offset 4 (dk + 4) = 4 ((0x80 + dk) - 0x7c)
-    b.a0 = (b0 - 0x7C7C7C7Cu) << 2;
-    b.a1 = (b1 - 0x7C7C7C7Cu) << 2;
+    potts_maps_a(make_uint2(b0, b1), b);
     return make_uint2(b0, b1);
 }
 
@@ -1050,6 +1066,53 @@ __device__ __forceinline__ PottsBulk potts_bulk(uint32_t cur, uint32_t prv, uint
 
 __device__ __forceinline__ int32_t row_step(const PottsBulk &b, bool left_flipped, int j) {
     return 36 * (left_flipped ? sbyte(b.k1, j) : sbyte(b.k0, j));
+}
+
+// Producer side of the Potts bulk for one dword: (B0, B1, M, sp) with
+// B = (X | 0x80808080) - Y over the down, right and left terms (the right term
+// of a row's last site and the left proposal term of a dword's first site
+// left out), M = bit s0 | bit (8 + s'0) of the first site (zero at a row
+// start, whose candidates agree), and the proposals sp.
+__device__ __forceinline__ uint4 potts_pre(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t dn, uint32_t tq4,
+                                           bool row_start, bool row_end) {
+    const uint32_t sp = (cur + 0x01010101u + tq4) & 0x07070707u;
+    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
+    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);
+    const uint32_t ln = sp << 8;   // left proposals of sites 1..3
+    const uint32_t rmask = row_end ? 0x00FFFFFFu : 0xFFFFFFFFu;
+    const uint32_t P2 = eq8(dn, cur) + (eq8(rn, cur) & rmask);
+    const uint32_t Q2 = eq8(dn, sp) + (eq8(rn, sp) & rmask);
+    const uint32_t lc = eq8(lo, cur), ls = eq8(lo, sp);
+    uint32_t nc = eq8(ln, cur) & 0xFFFFFF00u, ns = eq8(ln, sp) & 0xFFFFFF00u;
+    if (row_start) {
+        nc |= lc & 0xFFu;
+        ns |= ls & 0xFFu;
+    }
+    const uint32_t B0 = ((P2 + lc) | 0x80808080u) - (Q2 + ls);
+    const uint32_t B1 = ((P2 + nc) | 0x80808080u) - (Q2 + ns);
+    const uint32_t M = row_start ? 0u : ((1u << (cur & 7u)) | (1u << (8u + (sp & 7u))));
+    return make_uint4(B0, B1, M, sp);
+}
+
+// Walker side: the up terms added to the producer's counts.
+__device__ __forceinline__ uint2 potts_up(uint32_t cur, uint32_t up, const uint4 &pe) {
+    const uint32_t eu = eq8(up, cur), es = eq8(up, pe.w);
+    return make_uint2(pe.x + eu - es, pe.y + eu - es);
+}
+
+// A row's last site: its right neighbour is the row's first site, updated
+// earlier in this sweep (byte 0 of first).
+__device__ __forceinline__ uint2 potts_row_end(uint2 bd, uint32_t cur, uint32_t sp, uint32_t first) {
+    const uint32_t t = first << 24;
+    const uint32_t x3 = eq8(t, cur) & 0xFF000000u, y3 = eq8(t, sp) & 0xFF000000u;
+    return make_uint2(bd.x + x3 - y3, bd.y + x3 - y3);
+}
+
+// A dword's first site with its left neighbour accepted: that neighbour holds
+// its proposal (byte 3 of sp_prv), compared through the producer's bit mask.
+__device__ __forceinline__ uint32_t potts_left(uint32_t b1, uint32_t M, uint32_t sp_prv) {
+    const uint32_t v = sp_prv >> 24;
+    return b1 + __builtin_amdgcn_ubfe(M, v, 1u) - __builtin_amdgcn_ubfe(M, v + 8u, 1u);
 }
 
 template <int L>
@@ -1072,8 +1135,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
     const uint32_t ringu0 = lbase + (uint32_t)plan.off_ring;                    // [3][lane][CDW+1] uint4
     const uint32_t ubuf = (uint32_t)nch * (CDW + 1) * 16u;
-    const uint32_t ringt0 = ringu0 + 3u * ubuf;                                 // [3][lane][CDW+1] uint32
-    const uint32_t tbuf = (uint32_t)nch * (CDW + 1) * 4u;
+    const uint32_t ringp0 = ringu0 + 3u * ubuf;                                 // [3][lane][CDW+1] uint4
 
     for (int j = tid; j < NW * nch; j += nthreads) {
         const int d = j / nch, c = j - d * nch;
@@ -1088,8 +1150,9 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     auto produce = [&](int t) {
         const int sw = t / NCH;
         const uint32_t sweep = sweep0 + (uint32_t)sw;
-        const int dw0 = (t - sw * NCH) * CDW;
-        const uint32_t bu = ringu0 + (uint32_t)(t % 3) * ubuf, bt = ringt0 + (uint32_t)(t % 3) * tbuf;
+        const int ci = t - sw * NCH;
+        const int dw0 = ci * CDW;
+        const uint32_t bu = ringu0 + (uint32_t)(t % 3) * ubuf, bp = ringp0 + (uint32_t)(t % 3) * ubuf;
         const int total = CDW * nch;
         for (int w = tid - 64; w < total; w += nthreads - 64) {
             const int c = w / CDW, q = w - c * CDW;
@@ -1101,7 +1164,17 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
             const uint32_t off = (uint32_t)(c * (CDW + 1) + q);
             lds_st4(bu + off * 16u, make_uint4(min(b0.y, 0xFFFFFFFEu), min(b0.w, 0xFFFFFFFEu),
                                                min(b1.y, 0xFFFFFFFEu), min(b1.w, 0xFFFFFFFEu)));
-            lds_st(bt + off * 4u, t0 | (t1 << 8) | (t2 << 16) | (t3 << 24));
+            // lattice terms of the dword (row y, dword x of chain c)
+            const int r = q / W, x = q - r * W;
+            const int y = ci * RPC + r;
+            const uint32_t lb = spin0 + (uint32_t)(c * P) * 4u;
+            const uint32_t rowb = lb + (uint32_t)(y * W) * 4u;
+            const uint32_t cur = lds_ld(rowb + 4u * (uint32_t)x);
+            const uint32_t prv = lds_ld(rowb + 4u * (uint32_t)(x == 0 ? W - 1 : x - 1));
+            const uint32_t nxt = lds_ld(rowb + 4u * (uint32_t)(x + 1 == W ? x : x + 1));
+            const uint32_t dn = lds_ld(lb + (uint32_t)(((y + 1 == L) ? 0 : y + 1) * W + x) * 4u);
+            lds_st4(bp + off * 16u, potts_pre(cur, prv, nxt, dn, t0 | (t1 << 8) | (t2 << 16) | (t3 << 24), x == 0,
+                                             x + 1 == W));
         }
     };
 
@@ -1114,7 +1187,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     const uint32_t sb = spin0 + (uint32_t)(lane * P) * 4u;
     const uint32_t rbu = ringu0 + (uint32_t)(lane * (CDW + 1)) * 16u;
-    const uint32_t rbt = ringt0 + (uint32_t)(lane * (CDW + 1)) * 4u;
+    const uint32_t rbp = ringp0 + (uint32_t)(lane * (CDW + 1)) * 16u;
     auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
 
     FastState st{0, 0, 0, 0, false};
@@ -1124,9 +1197,15 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
         st.R = tab0 + ROWB * (uint32_t)k;
         st.C = st.R;
-        const uint32_t r0 = row_addr(0), rl = row_addr(L - 1), r1 = row_addr(1);
-        nb = potts_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(rl), lds_ld(r1),
-                              lds_ld(rbt), 0u);
+        const uint32_t r0 = row_addr(0), rl = row_addr(L - 1);
+        // dword 0 of chunk 0 (a row start): the producer's terms and the up row
+        const uint4 pe0 = lds_ld4(rbp);
+        const uint32_t c0 = lds_ld(r0);
+        const uint2 bd0 = potts_up(c0, lds_ld(rl), pe0);
+        potts_maps_a(bd0, nb);
+        potts_steps(bd0, nb);
+        nb.cur = c0;
+        nb.sp = pe0.w;
         st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
         st.tB = st.tA;
     }
@@ -1136,51 +1215,47 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
             if (active) {
                 const int ci = t % NCH;
                 const uint32_t ub = rbu + (uint32_t)(t % 3) * ubuf;
-                const uint32_t tb = rbt + (uint32_t)(t % 3) * tbuf;
-                const uint32_t tbn = rbt + (uint32_t)((t + 1) % 3) * tbuf;   // next chunk's offsets
+                const uint32_t pb = rbp + (uint32_t)(t % 3) * ubuf;
+                const uint32_t pbn = rbp + (uint32_t)((t + 1) % 3) * ubuf;   // next chunk's lattice terms
 #pragma unroll
                 for (int r = 0; r < RPC; ++r) {
                     const int y = ci * RPC + r;
                     const uint32_t vcur = row_addr(y);
                     const int yn = (y + 1 == L) ? 0 : y + 1;
                     const uint32_t vnc = row_addr(yn);
-                    const uint32_t vnd = row_addr(yn + 1 == L ? 0 : yn + 1);
                     const uint32_t vup = row_addr(y == 0 ? L - 1 : y - 1);
-                    const uint32_t vdn = vnc;
-                    uint32_t nxt_cache = lds_ld(vcur + 4);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const PottsBulk b = nb;
                         const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
                         // the next dword's bulk, in pieces between this dword's sites
-                        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
-                        PottsSums ns{0, 0, 0, 0, 0, 0};
+                        uint32_t ncur = 0, nup = 0, first = 0;
+                        uint4 pe = make_uint4(0, 0, 0, 0);
                         uint2 bd = make_uint2(0, 0);
                         auto work = [&](int j) {
                             if (j == 0) {
                                 if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
                                 if (w + 1 < W) {
-                                    q0 = nxt_cache;
-                                    q1 = b.cur;
-                                    q2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
-                                    q3 = lds_ld(vup + 4 * (w + 1));
-                                    q4 = lds_ld(vdn + 4 * (w + 1));
-                                    q5 = lds_ld(tb + (uint32_t)(r * W + w + 1) * 4u);
+                                    ncur = lds_ld(vcur + 4 * (w + 1));
+                                    nup = lds_ld(vup + 4 * (w + 1));
+                                    pe = lds_ld4(pb + (uint32_t)(r * W + w + 1) * 16u);
+                                    if (w + 2 == W) first = lds_ld(vcur);   // the row's first dword, this sweep
                                 } else {
-                                    q0 = lds_ld(vnc);
-                                    q1 = lds_ld(vnc + 4 * (W - 1));
-                                    q2 = lds_ld(vnc + 4);
-                                    q3 = lds_ld(vcur);
-                                    q4 = lds_ld(vnd);
-                                    q5 = (r + 1 < RPC) ? lds_ld(tb + (uint32_t)((r + 1) * W) * 4u) : lds_ld(tbn);
+                                    // first dword of the next row: its upper row is this one (new)
+                                    ncur = lds_ld(vnc);
+                                    nup = lds_ld(vcur);
+                                    pe = (r + 1 < RPC) ? lds_ld4(pb + (uint32_t)((r + 1) * W) * 16u) : lds_ld4(pbn);
                                 }
                             } else if (j == 1) {
-                                ns = potts_sums(q0, q1, q2, q3, q4, q5, (w + 1 < W) ? b.sp : 0u);
-                                if (w + 1 < W) nxt_cache = q2;
+                                bd = potts_up(ncur, nup, pe);
+                                if (w + 2 == W) bd = potts_row_end(bd, ncur, pe.w, first);
                             } else if (j == 2) {
-                                bd = (w + 1 < W) ? potts_cols<false>(ns, nb) : potts_cols<true>(ns, nb);
+                                bd.y = potts_left(bd.y, pe.z, b.sp);
+                                potts_maps_a(bd, nb);
                             } else {
                                 potts_steps(bd, nb);
+                                nb.cur = ncur;
+                                nb.sp = pe.w;
                             }
                         };
                         const uint32_t mask = walk_dword<PottsBulk, 0xFFu, 8>(st, b, nb, u, work);
