@@ -118,10 +118,11 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
     }
     if (fast_ising_ok(p, n_producer_waves)) {
         // lane-major lattice with an odd dword stride; ring [2][lane][chunk dwords + 1] uint4
+        // of words followed by [2][lane][chunk dwords + 1] uint2 of lattice terms
         const int W = p.L / 4;
         const int cdw = fast_rows_per_chunk(p.L) * W;
         l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
-        l.total = l.off_ring + 2 * it.nchains * (cdw + 1) * 16;
+        l.total = l.off_ring + 2 * it.nchains * (cdw + 1) * 24;
         return l;
     }
     if (fast_potts_ok(p, n_producer_waves)) {
@@ -567,6 +568,22 @@ __device__ __forceinline__ int lattice_bonds(uint32_t sb) {
     return k;
 }
 
+// Producer side of the Ising bulk for one dword: the candidate counts D0, D1
+// over the down, right and left neighbours (without the row above, which the
+// walker is updating, and without the right neighbour of a row's last site,
+// the row's first site of this sweep).  At a row start both candidates agree.
+__device__ __forceinline__ uint2 ising_pre(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t dn, bool row_start,
+                                           bool row_end) {
+    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
+    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);
+    const uint32_t s2 = (cur ^ dn) + ((cur ^ rn) & (row_end ? 0x00FFFFFFu : 0xFFFFFFFFu));
+    const uint32_t ml = cur ^ lo;
+    const uint32_t p0 = s2 + ml;
+    uint32_t p1 = s2 + (ml ^ 0x01010101u);
+    if (row_start) p1 = (p1 & 0xFFFFFF00u) | (p0 & 0xFFu);
+    return make_uint2(p0, p1);
+}
+
 template <int L, bool MAG>
 __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
@@ -587,7 +604,9 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     const uint32_t tab0 = lbase + (uint32_t)plan.off_tab;
     const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
     const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
-    const uint32_t ringbuf = (uint32_t)nch * (CDW + 1) * 16u;   // bytes per ring buffer
+    const uint32_t ringbuf = (uint32_t)nch * (CDW + 1) * 16u;   // bytes per ring buffer of words
+    const uint32_t ringp0 = ring0 + 2u * ringbuf;                // [2][lane][CDW+1] uint2 lattice terms
+    const uint32_t pbuf = (uint32_t)nch * (CDW + 1) * 8u;
 
     // stage the lattice: lane c's dword d = sites 4d..4d+3 of chain chain0 + c
     for (int j = tid; j < NW * nch; j += nthreads) {
@@ -601,6 +620,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     const uint32_t sb = spin0 + (uint32_t)(lane * P) * 4u;   // this lane's lattice
     const uint32_t rb = ring0 + (uint32_t)(lane * (CDW + 1)) * 16u;
+    const uint32_t rbp = ringp0 + (uint32_t)(lane * (CDW + 1)) * 8u;
     auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
 
     FastState st{0, 0, 0, 0, false};
@@ -616,12 +636,18 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
         st.tB = st.tA;
     }
 
-    // producers: chunk t covers rows (t mod NCH) * RPC .. + RPC - 1 of sweep t / NCH
+    // producers: chunk t covers rows (t mod NCH) * RPC .. + RPC - 1 of sweep t / NCH.
+    // One chunk ahead of the walker, the rows of the chunk and the row below it
+    // hold their final values of the previous sweep (below the last row: row
+    // 0 of this sweep), so the producers also form the lattice terms that do
+    // not involve the row above.
     auto produce = [&](int t) {
         const int sw = t / NCH;
         const uint32_t sweep = sweep0 + (uint32_t)sw;
-        const int blk0 = (t - sw * NCH) * CDW;   // Philox block of the chunk's first dword
+        const int ci = t - sw * NCH;
+        const int blk0 = ci * CDW;   // Philox block of the chunk's first dword
         const uint32_t buf = ring0 + (uint32_t)(t & 1) * ringbuf;
+        const uint32_t bp = ringp0 + (uint32_t)(t & 1) * pbuf;
         const int total = CDW * nch;
         for (int w = tid - 64; w < total; w += nthreads - 64) {
             const int c = w / CDW, q = w - c * CDW;
@@ -630,6 +656,17 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
             lds_st4(buf + (uint32_t)(c * (CDW + 1) + q) * 16u,
                     make_uint4(min(b.x, 0xFFFFFFFEu), min(b.y, 0xFFFFFFFEu), min(b.z, 0xFFFFFFFEu),
                                min(b.w, 0xFFFFFFFEu)));
+            const int r = q / W, x = q - r * W;
+            const int y = ci * RPC + r;
+            const uint32_t lb = spin0 + (uint32_t)(c * P) * 4u;
+            const uint32_t rowb = lb + (uint32_t)(y * W) * 4u;
+            const uint32_t cur = lds_ld(rowb + 4u * (uint32_t)x);
+            const uint32_t prv = lds_ld(rowb + 4u * (uint32_t)(x == 0 ? W - 1 : x - 1));
+            const uint32_t nxt = lds_ld(rowb + 4u * (uint32_t)(x + 1 == W ? x : x + 1));
+            const uint32_t dn = lds_ld(lb + (uint32_t)(((y + 1 == L) ? 0 : y + 1) * W + x) * 4u);
+            const uint2 pe = ising_pre(cur, prv, nxt, dn, x == 0, x + 1 == W);
+            lds_st(bp + (uint32_t)(c * (CDW + 1) + q) * 8u, pe.x);
+            lds_st(bp + (uint32_t)(c * (CDW + 1) + q) * 8u + 4u, pe.y);
         }
     };
 
@@ -642,6 +679,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
             if (active) {
                 const int ci = t % NCH;                 // chunk within the sweep
                 const uint32_t ub = rb + (uint32_t)(t & 1) * ringbuf;
+                const uint32_t pb = rbp + (uint32_t)(t & 1) * pbuf;
 #pragma unroll
                 for (int r = 0; r < RPC; ++r) {
                     const int y = ci * RPC + r;
@@ -651,28 +689,35 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                     const uint32_t vnc = row_addr(yn);
                     const uint32_t vnd = row_addr(yn + 1 == L ? 0 : yn + 1);
                     const uint32_t vup = row_addr(y == 0 ? L - 1 : y - 1);
-                    const uint32_t vdn = vnc;
-                    uint32_t nxt_cache = lds_ld(vcur + 4);   // old dword 1
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const FastBulk b = nb;
                         // random words of this dword (prefetched one dword ahead inside the chunk)
                         const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
                         // the next dword's bulk, in pieces between this dword's sites
-                        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;
+                        // (within the chunk from the producers' lattice terms; the next
+                        // chunk's first dword, whose terms are still being formed, in full)
+                        const bool in_chunk = (w + 1 < W) || (r + 1 < RPC);
+                        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, first = 0;
+                        uint2 pe = make_uint2(0, 0);
                         BulkSums ns{0, 0, 0};
                         BulkDiff nd{0, 0, 0};
                         auto work = [&](int j) {
                             if (j == 0) {
                                 if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
                                 if (w + 1 < W) {
-                                    q0 = nxt_cache;                                        // old dword w+1
-                                    q1 = b.cur;
-                                    q2 = lds_ld(vcur + 4 * ((w + 2 < W) ? w + 2 : 0));
+                                    q0 = lds_ld(vcur + 4 * (w + 1));                          // old dword w+1
                                     q3 = lds_ld(vup + 4 * (w + 1));
-                                    q4 = lds_ld(vdn + 4 * (w + 1));
+                                    pe.x = lds_ld(pb + (uint32_t)(r * W + w + 1) * 8u);
+                                    pe.y = lds_ld(pb + (uint32_t)(r * W + w + 1) * 8u + 4u);
+                                    if (w + 2 == W) first = lds_ld(vcur);   // the row's first dword, this sweep
+                                } else if (in_chunk) {
+                                    q0 = lds_ld(vnc);
+                                    q3 = lds_ld(vcur);                   // upper row: this one (new)
+                                    pe.x = lds_ld(pb + (uint32_t)((r + 1) * W) * 8u);
+                                    pe.y = lds_ld(pb + (uint32_t)((r + 1) * W) * 8u + 4u);
                                 } else {
-                                    // first dword of the next row: its upper row is this one (new)
+                                    // first dword of the next chunk: all neighbours here
                                     q0 = lds_ld(vnc);
                                     q1 = lds_ld(vnc + 4 * (W - 1));
                                     q2 = lds_ld(vnc + 4);
@@ -680,10 +725,20 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                                     q4 = lds_ld(vnd);
                                 }
                             } else if (j == 1) {
-                                ns = bulk_sums(q0, q1, q2, q3, q4);
-                                if (w + 1 < W) nxt_cache = q2;
+                                if (in_chunk) {
+                                    const uint32_t xu = q0 ^ q3;
+                                    uint32_t d0 = pe.x + xu, d1 = pe.y + xu;
+                                    if (w + 2 == W) {
+                                        const uint32_t cr = (q0 ^ (first << 24)) & 0xFF000000u;
+                                        d0 += cr;
+                                        d1 += cr;
+                                    }
+                                    nd = BulkDiff{q0, d0, d1};
+                                } else {
+                                    ns = bulk_sums(q0, q1, q2, q3, q4);
+                                }
                             } else if (j == 2) {
-                                nd = (w + 1 < W) ? bulk_diff<false>(ns) : bulk_diff<true>(ns);
+                                if (!in_chunk) nd = bulk_diff<true>(ns);
                                 bulk_cols<MAG>(nd, nb);
                             } else {
                                 bulk_steps<MAG>(nd, nb);
@@ -1144,6 +1199,7 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                            ((uint32_t)g[3 * (int64_t)p.C] << 24);
         lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
     }
+    __syncthreads();   // the producers read the staged lattice
 
     // producers: chunk t covers rows (t mod NCH) * RPC .. + RPC - 1 of sweep t / NCH;
     // one work unit is one dword (two Philox blocks of two sites each)
