@@ -625,7 +625,15 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 
     FastState st{0, 0, 0, 0, false};
     FastBulk nb{0, 0, 0, 0, 0};
+    // the row above the current row, as updated in this sweep (dword w of the
+    // current row replaces it once written): the walker's own stores, kept in
+    // registers
+    uint32_t upr[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) upr[w] = 0;
     if (active) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) upr[w] = lds_ld(row_addr(L - 1) + 4u * w);
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
         st.R = MAG ? tab0 + RB * (uint32_t)((((const g_i32 *)p.m)[it.chain0 + lane] + L * L) / 2)
                    : tab0 + RB * (uint32_t)(k >> 1);
@@ -688,7 +696,6 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                     const int yn = (y + 1 == L) ? 0 : y + 1;
                     const uint32_t vnc = row_addr(yn);
                     const uint32_t vnd = row_addr(yn + 1 == L ? 0 : yn + 1);
-                    const uint32_t vup = row_addr(y == 0 ? L - 1 : y - 1);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const FastBulk b = nb;
@@ -707,13 +714,13 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                                 if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
                                 if (w + 1 < W) {
                                     q0 = lds_ld(vcur + 4 * (w + 1));                          // old dword w+1
-                                    q3 = lds_ld(vup + 4 * (w + 1));
+                                    q3 = upr[w + 1];
                                     pe.x = lds_ld(pb + (uint32_t)(r * W + w + 1) * 8u);
                                     pe.y = lds_ld(pb + (uint32_t)(r * W + w + 1) * 8u + 4u);
-                                    if (w + 2 == W) first = lds_ld(vcur);   // the row's first dword, this sweep
+                                    if (w + 2 == W) first = upr[0];   // the row's first dword, this sweep
                                 } else if (in_chunk) {
                                     q0 = lds_ld(vnc);
-                                    q3 = lds_ld(vcur);                   // upper row: this one (new)
+                                    q3 = upr[0];                         // upper row: this one (new)
                                     pe.x = lds_ld(pb + (uint32_t)((r + 1) * W) * 8u);
                                     pe.y = lds_ld(pb + (uint32_t)((r + 1) * W) * 8u + 4u);
                                 } else {
@@ -721,7 +728,7 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                                     q0 = lds_ld(vnc);
                                     q1 = lds_ld(vnc + 4 * (W - 1));
                                     q2 = lds_ld(vnc + 4);
-                                    q3 = lds_ld(vcur);
+                                    q3 = upr[0];
                                     q4 = lds_ld(vnd);
                                 }
                             } else if (j == 1) {
@@ -745,7 +752,8 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                             }
                         };
                         const uint32_t f = walk_dword<FastBulk, 1u, 8>(st, b, nb, u, work);
-                        lds_st(vcur + 4 * w, b.cur ^ f);
+                        upr[w] = b.cur ^ f;
+                        lds_st(vcur + 4 * w, upr[w]);
                     }
                     if (y == L - 1 && l.record != kRecNone) {
                         const uint32_t Rk = st.acc ? st.C : st.R;
@@ -1123,11 +1131,12 @@ __device__ __forceinline__ int32_t row_step(const PottsBulk &b, bool left_flippe
     return 36 * (left_flipped ? sbyte(b.k1, j) : sbyte(b.k0, j));
 }
 
-// Producer side of the Potts bulk for one dword: (B0, B1, M, sp) with
+// Producer side of the Potts bulk for one dword: (B0, B1 - 1, T, sp) with
 // B = (X | 0x80808080) - Y over the down, right and left terms (the right term
 // of a row's last site and the left proposal term of a dword's first site
-// left out), M = bit s0 | bit (8 + s'0) of the first site (zero at a row
-// start, whose candidates agree), and the proposals sp.
+// left out), T a table of 1 + [v = s0] - [v = s'0] in two bits per value v of
+// the first site's left proposal (all 1 at a row start, whose candidates
+// agree), and the proposals sp.
 __device__ __forceinline__ uint4 potts_pre(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t dn, uint32_t tq4,
                                            bool row_start, bool row_end) {
     const uint32_t sp = (cur + 0x01010101u + tq4) & 0x07070707u;
@@ -1145,8 +1154,8 @@ __device__ __forceinline__ uint4 potts_pre(uint32_t cur, uint32_t prv, uint32_t 
     }
     const uint32_t B0 = ((P2 + lc) | 0x80808080u) - (Q2 + ls);
     const uint32_t B1 = ((P2 + nc) | 0x80808080u) - (Q2 + ns);
-    const uint32_t M = row_start ? 0u : ((1u << (cur & 7u)) | (1u << (8u + (sp & 7u))));
-    return make_uint4(B0, B1, M, sp);
+    const uint32_t T = row_start ? 0x5555u : 0x5555u + (1u << (2u * (cur & 7u))) - (1u << (2u * (sp & 7u)));
+    return make_uint4(B0, B1 - 1u, T, sp);
 }
 
 // Walker side: the up terms added to the producer's counts.
@@ -1164,10 +1173,11 @@ __device__ __forceinline__ uint2 potts_row_end(uint2 bd, uint32_t cur, uint32_t 
 }
 
 // A dword's first site with its left neighbour accepted: that neighbour holds
-// its proposal (byte 3 of sp_prv), compared through the producer's bit mask.
-__device__ __forceinline__ uint32_t potts_left(uint32_t b1, uint32_t M, uint32_t sp_prv) {
-    const uint32_t v = sp_prv >> 24;
-    return b1 + __builtin_amdgcn_ubfe(M, v, 1u) - __builtin_amdgcn_ubfe(M, v + 8u, 1u);
+// its proposal v (byte 3 of sp_prv), looked up in the producer's table at bit
+// 2v = sp_prv >> 23 (byte 2 of sp_prv is at most 7).  The table entry carries
+// the +1 that the producer took off B1.
+__device__ __forceinline__ uint32_t potts_left(uint32_t b1, uint32_t T, uint32_t sp_prv) {
+    return b1 + __builtin_amdgcn_ubfe(T, sp_prv >> 23, 2u);
 }
 
 template <int L>
@@ -1249,7 +1259,13 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
     FastState st{0, 0, 0, 0, false};
     uint4 u_next = make_uint4(0, 0, 0, 0);
     PottsBulk nb{0, 0, 0, 0, 0, 0};
+    // the row above, as updated in this sweep: the walker's own stores
+    uint32_t upr[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) upr[w] = 0;
     if (active) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) upr[w] = lds_ld(row_addr(L - 1) + 4u * w);
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
         st.R = tab0 + ROWB * (uint32_t)k;
         st.C = st.R;
@@ -1257,7 +1273,8 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
         // dword 0 of chunk 0 (a row start): the producer's terms and the up row
         const uint4 pe0 = lds_ld4(rbp);
         const uint32_t c0 = lds_ld(r0);
-        const uint2 bd0 = potts_up(c0, lds_ld(rl), pe0);
+        uint2 bd0 = potts_up(c0, lds_ld(rl), pe0);
+        bd0.y += 1u;   // a row start: its table entry is 1 whatever the left proposal
         potts_maps_a(bd0, nb);
         potts_steps(bd0, nb);
         nb.cur = c0;
@@ -1279,7 +1296,6 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                     const uint32_t vcur = row_addr(y);
                     const int yn = (y + 1 == L) ? 0 : y + 1;
                     const uint32_t vnc = row_addr(yn);
-                    const uint32_t vup = row_addr(y == 0 ? L - 1 : y - 1);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const PottsBulk b = nb;
@@ -1293,13 +1309,13 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                                 if (r * W + w + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(r * W + w + 1) * 16u);
                                 if (w + 1 < W) {
                                     ncur = lds_ld(vcur + 4 * (w + 1));
-                                    nup = lds_ld(vup + 4 * (w + 1));
+                                    nup = upr[w + 1];
                                     pe = lds_ld4(pb + (uint32_t)(r * W + w + 1) * 16u);
-                                    if (w + 2 == W) first = lds_ld(vcur);   // the row's first dword, this sweep
+                                    if (w + 2 == W) first = upr[0];   // the row's first dword, this sweep
                                 } else {
                                     // first dword of the next row: its upper row is this one (new)
                                     ncur = lds_ld(vnc);
-                                    nup = lds_ld(vcur);
+                                    nup = upr[0];
                                     pe = (r + 1 < RPC) ? lds_ld4(pb + (uint32_t)((r + 1) * W) * 16u) : lds_ld4(pbn);
                                 }
                             } else if (j == 1) {
@@ -1315,7 +1331,8 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
                             }
                         };
                         const uint32_t mask = walk_dword<PottsBulk, 0xFFu, 8>(st, b, nb, u, work);
-                        lds_st(vcur + 4 * w, (mask & b.sp) | (~mask & b.cur));
+                        upr[w] = (mask & b.sp) | (~mask & b.cur);
+                        lds_st(vcur + 4 * w, upr[w]);
                     }
                     if (y == L - 1 && l.record != kRecNone) {
                         const uint32_t Rk = st.acc ? st.C : st.R;
