@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,11 +34,20 @@ OPS_PER_ISING_UPDATE = 32
 PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9
 
 
-def kernel_source_hash() -> str:
+def code_text(src: str) -> str:
+    """C++ source without comments and with whitespace collapsed, so that a
+    change of comments alone leaves the hash below unchanged."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_source_hash(root: str = ROOT) -> str:
+    """Hash of the sweep kernel's code (comments excluded)."""
     h = hashlib.sha256()
     for f in ("muca_kernels.hip", "muca_device.h"):
-        with open(os.path.join(ROOT, "paper_1212_3975_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, "paper_1212_3975_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -5,11 +5,12 @@
 // chains: one lane per chain.  A workgroup owns up to 64 chains of one
 // problem.  Its first wave is the walker: lane c runs chain chain0 + c
 // through the sites in order.  Optionally 1..3 more waves are producers:
-// they draw the Philox words of the next chunk of sites for every chain into
-// an LDS double buffer while the walker consumes the current chunk, so the
-// walker issues no multiplies.  The lattice (uint8 per site, chain fastest)
-// and the acceptance table can each live in LDS or in HBM; the host picks
-// the placement per problem.
+// they draw the Philox words of a later chunk of sites for every chain into
+// an LDS ring while the walker consumes the current chunk, so the walker
+// issues no multiplies; for the fast walkers they also form the lattice
+// terms of that chunk that the walker's updates can no longer change.  The
+// lattice (uint8 per site, chain fastest) and the acceptance table can each
+// live in LDS or in HBM; the host picks the placement per problem.
 #include "muca_device.h"
 
 namespace muca {
@@ -416,8 +417,11 @@ __device__ __forceinline__ void walk_chunk(const ProbDev &p, const WorkItem &it,
 // Layout: each lane's lattice is contiguous in LDS (row-major dwords, an odd
 // dword stride between lanes so that lanes hit different banks); L is a
 // compile-time constant, so every neighbour read is a fixed offset from one
-// of three row pointers.  The random words of a chunk of rows sit in a ring
-// [buffer][lane][dword] of uint4.
+// of a few row pointers.  The row above the current one is the walker's own
+// output and stays in registers.  The producers fill, per chunk of rows, a
+// ring [buffer][lane][dword] of uint4 random words followed by a ring of the
+// dword's lattice terms that do not involve the row above (uint2 counts for
+// Ising, uint4 for Potts).
 
 __device__ __forceinline__ uint32_t ubyte(uint32_t v, int j) { return (v >> (8 * j)) & 0xFFu; }
 __device__ __forceinline__ int32_t sbyte(uint32_t v, int j) { return (int32_t)(int8_t)(uint8_t)(v >> (8 * j)); }

@@ -1,0 +1,15 @@
+"""Host helpers of the benchmark: the kernel code hash that ties the committed
+counter profile to the kernel it was taken on."""
+import bench
+
+
+def test_code_text_ignores_comments_and_layout():
+    a = "int f(int x) {\n  // one\n  return x + 1; /* two\n three */\n}\n"
+    b = "int f(int x) { return x + 1; }"
+    assert bench.code_text(a) == bench.code_text(b)
+    assert bench.code_text(a) != bench.code_text("int f(int x) { return x + 2; }")
+
+
+def test_kernel_source_hash_is_stable():
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and h == bench.kernel_source_hash()
