@@ -83,13 +83,20 @@ def cpu_baseline(prob, sweeps: int, n_chains: int):
                       f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
 
 
-def scan_chains(L, pm, torch, Problem, ISING):
-    """Sweep-kernel throughput of Ising L x L versus the number of chains (tuned
-    launch per count): the walkers are serial per chain, so throughput grows
-    with the chain count until the chip's LDS holds no more walkers."""
+OPS_PER_POTTS_UPDATE = 62   # half a Philox block, the proposal and twice the compares
+
+
+def scan_chains(L, pm, torch, Problem, model):
+    """Sweep-kernel throughput of Ising or 8-state Potts L x L versus the
+    number of chains (tuned launch per count): the walkers are serial per
+    chain, so throughput grows with the chain count until the chip's LDS holds
+    no more walkers."""
+    from workloads import POTTS
+    potts = model == POTTS
+    ops = OPS_PER_POTTS_UPDATE if potts else OPS_PER_ISING_UPDATE
     rows = []
     for chains in (1024, 2048, 4096, 8192, 16384, 32768, 65536):
-        prob = Problem(ISING, L, chains, 7)
+        prob = Problem(model, L, chains, 7, q=8) if potts else Problem(model, L, chains, 7)
         ctx = pm.Muca([prob], device="cuda:0", production=0)
         sweeps = max(20, int(4e9 / (chains * L * L)))
         ctx.sweep(sweeps, pm.REC_NONE)   # warm-up
@@ -100,12 +107,13 @@ def scan_chains(L, pm, torch, Problem, ISING):
         info = ctx.launch_info()
         ctx.close()
         rows.append({"chains": chains, "sweeps": sweeps, "kernel_ms": round(ms, 3), "Gups": round(rate / 1e9, 2),
-                     "alu_frac": round(OPS_PER_ISING_UPDATE * rate / PEAK_INT32_OPS, 4),
+                     "alu_frac": round(ops * rate / PEAK_INT32_OPS, 4),
                      "chains_per_wg": info["chains_per_wg"], "fast_walker": info["fast_walker"],
                      "workgroups": info["n_workgroups"]})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    name = f"2D 8-state Potts L={L}" if potts else f"2D Ising L={L}"
     print(json.dumps({"metric": "sweep-kernel spin-update attempts/s vs chains", "unit": "G/s",
-                      "workload": f"2D Ising L={L}", "rows": rows}), flush=True)
+                      "workload": name, "ops_per_update": ops, "rows": rows}), flush=True)
 
 
 def main():
@@ -122,7 +130,9 @@ def main():
     ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed", "mag32"])
     ap.add_argument("--graph", action="store_true", help="run each iteration as one HIP graph launch")
     ap.add_argument("--scan-chains", type=int, default=0, metavar="L",
-                    help="instead of the benchmark: sweep throughput of Ising L x L versus the number of chains")
+                    help="instead of the benchmark: sweep throughput of an L x L lattice versus the number of chains")
+    ap.add_argument("--scan-model", default="ising", choices=["ising", "potts8"],
+                    help="model of --scan-chains")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size kernel for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -137,7 +147,8 @@ def main():
     from workloads import C2, C3, C4, C_MAG, ISING, Problem
 
     if args.scan_chains:
-        scan_chains(args.scan_chains, pm, torch, Problem, ISING)
+        from workloads import POTTS
+        scan_chains(args.scan_chains, pm, torch, Problem, POTTS if args.scan_model == "potts8" else ISING)
         return
 
     if args.copy_calibration:
@@ -228,7 +239,8 @@ def main():
     }
     ctx.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, 2000, 128 if prob.model == 0 else 256)
+        # about 10-15 s of the oracle on 16 host threads
+        out["cpu_baseline"] = cpu_baseline(prob, 2000, 2048 if prob.model != 1 else 4096)
     print(json.dumps(out), flush=True)
 
 
