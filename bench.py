@@ -66,6 +66,17 @@ def measured_traffic(updates_per_launch: int):
     return None if per_update is None else per_update * updates_per_launch
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(prob, sweeps: int, n_chains: int):
     """The oracle as it stands, on the host cores, on a bounded sample of the
     same workload: n_chains chains for `sweeps` sweeps."""
@@ -78,7 +89,7 @@ def cpu_baseline(prob, sweeps: int, n_chains: int):
     dt = time.perf_counter() - t0
     ups = n_chains * sweeps * prob.N / dt
     return {"value": round(ups / 1e9, 4), "unit": "G/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_chains} chains x {sweeps} recorded sweeps of "
+            "sample": f"{host_cpu_model()}: {n_chains} chains x {sweeps} recorded sweeps of "
                       f"{['Ising', str(prob.q) + '-state Potts', 'multimagnetic Ising'][prob.model]} L={prob.L} "
                       f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
 
@@ -95,7 +106,7 @@ def scan_chains(L, pm, torch, Problem, model):
     potts = model == POTTS
     ops = OPS_PER_POTTS_UPDATE if potts else OPS_PER_ISING_UPDATE
     rows = []
-    for chains in (1024, 2048, 4096, 8192, 16384, 32768, 65536):
+    for chains in (1024, 2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144):
         prob = Problem(model, L, chains, 7, q=8) if potts else Problem(model, L, chains, 7)
         ctx = pm.Muca([prob], device="cuda:0", production=0)
         sweeps = max(20, int(4e9 / (chains * L * L)))
