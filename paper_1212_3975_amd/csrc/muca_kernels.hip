@@ -1070,30 +1070,6 @@ __device__ __forceinline__ uint32_t eq8(uint32_t a, uint32_t b) {
     return __builtin_amdgcn_perm(0u, 0x00000001u, a ^ b);
 }
 
-// The Potts bulk in three pieces: proposals and neighbour equalities; the
-// biased differences and column offsets; the row steps.
-struct PottsSums {
-    uint32_t cur, sp;          // old states, proposals
-    uint32_t X0, Y0, X1, Y1;   // equalities with s and with s', left neighbour old (0) or proposed (1)
-};
-
-__device__ __forceinline__ PottsSums potts_sums(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn,
-                                                uint32_t tq4, uint32_t sp_prv) {
-    PottsSums q;
-    q.cur = cur;
-    q.sp = (cur + 0x01010101u + tq4) & 0x07070707u;
-    const uint32_t rn = __builtin_amdgcn_alignbyte(nxt, cur, 1);
-    const uint32_t lo = __builtin_amdgcn_alignbyte(cur, prv, 3);        // left, old state
-    const uint32_t ln = __builtin_amdgcn_alignbyte(q.sp, sp_prv, 3);    // left, its proposal
-    const uint32_t P = eq8(up, cur) + eq8(dn, cur) + eq8(rn, cur);
-    const uint32_t Q = eq8(up, q.sp) + eq8(dn, q.sp) + eq8(rn, q.sp);
-    q.X0 = P + eq8(lo, cur);
-    q.Y0 = Q + eq8(lo, q.sp);
-    q.X1 = P + eq8(ln, cur);
-    q.Y1 = Q + eq8(ln, q.sp);
-    return q;
-}
-
 // Column byte offsets 4 (dk + 4) = 4 ((0x80 + dk) - 0x7c) of both candidates
 // from the biased differences.
 __device__ __forceinline__ void potts_maps_a(uint2 bd, PottsBulk &b) {
@@ -1101,34 +1077,9 @@ __device__ __forceinline__ void potts_maps_a(uint2 bd, PottsBulk &b) {
     b.a1 = (bd.y - 0x7C7C7C7Cu) << 2;
 }
 
-// Fills cur, sp, a0, a1 and returns the biased differences (0x80 + dk per byte).
-template <bool ROW_START>
-__device__ __forceinline__ uint2 potts_cols(const PottsSums &q, PottsBulk &b) {
-    uint32_t X1 = q.X1, Y1 = q.Y1;
-    if (ROW_START) {
-        // the first site's left neighbour (row end) has not been visited yet
-        X1 = (X1 & 0xFFFFFF00u) | (q.X0 & 0xFFu);
-        Y1 = (Y1 & 0xFFFFFF00u) | (q.Y0 & 0xFFu);
-    }
-    // dk = X - Y in [-4, 4]: biased bytes 0x80 + dk never borrow
-    const uint32_t b0 = (q.X0 | 0x80808080u) - q.Y0, b1 = (X1 | 0x80808080u) - Y1;
-    b.cur = q.cur;
-    b.sp = q.sp;
-    potts_maps_a(make_uint2(b0, b1), b);
-    return make_uint2(b0, b1);
-}
-
 __device__ __forceinline__ void potts_steps(uint2 bd, PottsBulk &b) {
     b.k0 = bd.x ^ 0x80808080u;
     b.k1 = bd.y ^ 0x80808080u;
-}
-
-template <bool ROW_START>
-__device__ __forceinline__ PottsBulk potts_bulk(uint32_t cur, uint32_t prv, uint32_t nxt, uint32_t up, uint32_t dn,
-                                                uint32_t tq4, uint32_t sp_prv) {
-    PottsBulk b;
-    potts_steps(potts_cols<ROW_START>(potts_sums(cur, prv, nxt, up, dn, tq4, sp_prv), b), b);
-    return b;
 }
 
 __device__ __forceinline__ int32_t row_step(const PottsBulk &b, bool left_flipped, int j) {
