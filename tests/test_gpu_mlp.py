@@ -3,7 +3,6 @@ reference with matched bfloat16 rounding (through the C ABI)."""
 import numpy as np
 import pytest
 
-import oracle
 from conftest import gpu_available
 from oracle import mlp_ref
 from workloads import ISING, Problem

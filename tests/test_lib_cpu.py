@@ -5,8 +5,6 @@ import ctypes
 import os
 import re
 
-import pytest
-
 import paper_1212_3975_amd as pm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
