@@ -86,7 +86,9 @@ typedef struct {
 /* Launch and iteration options; zero means "default / autotune".
  *   chains_per_wg    chains handled by one workgroup (16, 32 or 64; 0 = tune)
  *   rng_mode         0 = tune, 1 = walker draws its own numbers,
- *                    2 = helper waves of the workgroup draw them
+ *                    2, 3, 4 = one, two or three helper waves of the
+ *                    workgroup draw them (and, for the fast walkers, form
+ *                    the lattice terms the walker's updates cannot change)
  *   spin_placement   0 = tune, 1 = lattice in LDS, 2 = lattice in HBM
  *   table_placement  0 = tune, 1 = table in LDS, 2 = table in HBM
  *   use_graph        1 = mucaIterate replays one HIP graph per iteration

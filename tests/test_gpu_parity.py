@@ -378,3 +378,30 @@ def test_packed_l64_walker_bit_exact(chains, cw):
         cnt, sab = orc.production(0, 30)
         assert np.array_equal(ctx.prod_counts(), cnt) and np.array_equal(ctx.prod_absm(), sab)
         assert np.array_equal(ctx.spins(), orc.spins)
+
+
+@pytest.mark.parametrize("rng_mode", [2, 4], ids=["one-producer", "three-producers"])
+@pytest.mark.parametrize("prob,n_sweeps", [(Problem(ISING, 16, 40, 51), 3000), (Problem(POTTS, 16, 40, 52, q=8), 3000),
+                                           (Problem(ISING_MAG, 16, 40, 53, beta=0.66), 3000),
+                                           (Problem(POTTS, 24, 30, 54, q=8), 1500), (Problem(ISING, 64, 20, 55), 600)],
+                         ids=["isingL16", "pottsL16", "magL16", "pottsL24", "isingL64"])
+def test_fast_walkers_long_launch_bit_exact(prob, n_sweeps, rng_mode):
+    """One long launch of each fast walker with non-trivial weights: thousands
+    of chunk hand-offs between the producer waves (which read the lattice one or
+    two chunks ahead of the walker) and the walker, with one or three producer
+    waves.  L = 16 has four chunks per sweep, the fewest the walkers allow.
+    Trajectories, per-chain histograms and energies equal the oracle's."""
+    pm = _pm()
+    print("case", prob, n_sweeps, rng_mode, flush=True)
+    with pm.Muca([prob], rng_mode=rng_mode, chains_per_wg=16, spin_placement=1, table_placement=1) as ctx:
+        info = ctx.launch_info()
+        print("launch", info, flush=True)
+        assert info["fast_walker"] == 1
+        orc = _orc(prob)
+        _compare_iterations(ctx, orc, 1, 200)   # non-trivial weights
+        ctx.sweep(n_sweeps, pm.REC_MUCA)
+        orc.hist[:] = 0
+        orc.sweeps(n_sweeps, oracle.REC_MUCA)
+        assert np.array_equal(ctx.chain_hist(), orc.hist)
+        assert np.array_equal(ctx.spins(), orc.spins)
+        assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
