@@ -545,7 +545,15 @@ muca_status configure(muca_ctx ctx) {
             float best = 1e30f;
             ProbHost keep = h;
             bool any = false;
-            for (int cw : cw_cands) {
+            // besides the fixed sizes, the most chains whose lattice and table both fit in LDS
+            std::vector<int> cands = cw_cands;
+            if (!o.chains_per_wg && o.spin_placement != 2 && o.table_placement != 2) {
+                int top = 0;
+                for (int cw = 64; cw >= 1 && !top; --cw)
+                    if (fits(ctx, h, cw, 1, 1, nprod)) top = cw;
+                if (top && std::find(cands.begin(), cands.end(), top) == cands.end()) cands.push_back(top);
+            }
+            for (int cw : cands) {
                 if (!place(h, cw, nprod)) continue;
                 float ms = 0;
                 if ((st = time_config(ctx, {(int)pi}, o.tune_sweeps, &ms))) return st;

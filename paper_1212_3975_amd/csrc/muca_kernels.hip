@@ -104,6 +104,13 @@ __host__ __device__ inline bool packed_ising(const ProbDev &p, const WorkItem &i
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves);
 __host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves);
 __host__ __device__ constexpr int fast_rows_per_chunk(int L) { return (64 + L - 1) / L; }
+// Potts chunks: 64 sites or more up to 32 chains per workgroup, 32 or more
+// beyond (its ring has three buffers of two uint4 per dword, so smaller chunks
+// leave LDS for more chains; larger ones cost fewer barriers per site).
+__host__ __device__ constexpr bool potts_wide(int nchains) { return nchains > 32; }
+__host__ __device__ constexpr int potts_rows_per_chunk(int L, bool wide) {
+    return wide ? (32 + L - 1) / L : (64 + L - 1) / L;
+}
 __host__ __device__ constexpr int fast_lane_stride(int L) { return ((L * L / 4) % 2) ? L * L / 4 : L * L / 4 + 1; }
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
@@ -130,7 +137,7 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
         // lane-major lattice; ring of three buffers: [3][lane][chunk dwords + 1] uint4 words
         // followed by [3][lane][chunk dwords + 1] uint4 lattice terms
         const int W = p.L / 4;
-        const int cdw = fast_rows_per_chunk(p.L) * W;
+        const int cdw = potts_rows_per_chunk(p.L, potts_wide(it.nchains)) * W;
         l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
         l.total = l.off_ring + 3 * it.nchains * (cdw + 1) * 32;
         return l;
@@ -1135,12 +1142,12 @@ __device__ __forceinline__ uint32_t potts_left(uint32_t b1, uint32_t T, uint32_t
     return b1 + __builtin_amdgcn_ubfe(T, sp_prv >> 23, 2u);
 }
 
-template <int L>
+template <int L, bool WIDE>
 __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
     constexpr int W = L / 4;
     constexpr int NW = L * L / 4;
-    constexpr int RPC = fast_rows_per_chunk(L);
+    constexpr int RPC = potts_rows_per_chunk(L, WIDE);
     constexpr int CDW = RPC * W;
     constexpr int NCH = L / RPC;
     constexpr int P = fast_lane_stride(L);
@@ -1323,10 +1330,14 @@ __device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 __device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                             const SweepLaunch &l, uint32_t sweep0,
                                                             const LdsPlan &plan) {
+    const bool wide = potts_wide(it.nchains);
     switch (p.L) {
-    case 16: run_potts_fast<16>(p, it, lds, l, sweep0, plan); return true;
-    case 24: run_potts_fast<24>(p, it, lds, l, sweep0, plan); return true;
-    case 32: run_potts_fast<32>(p, it, lds, l, sweep0, plan); return true;
+    case 16: wide ? run_potts_fast<16, true>(p, it, lds, l, sweep0, plan)
+                  : run_potts_fast<16, false>(p, it, lds, l, sweep0, plan); return true;
+    case 24: wide ? run_potts_fast<24, true>(p, it, lds, l, sweep0, plan)
+                  : run_potts_fast<24, false>(p, it, lds, l, sweep0, plan); return true;
+    case 32: wide ? run_potts_fast<32, true>(p, it, lds, l, sweep0, plan)
+                  : run_potts_fast<32, false>(p, it, lds, l, sweep0, plan); return true;
     default: return false;
     }
 }
