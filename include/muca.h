@@ -84,9 +84,10 @@ typedef struct {
 } muca_problem;
 
 /* Launch and iteration options; zero means "default / autotune".
- *   chains_per_wg    chains handled by one workgroup (4, 8, 16, 32 or 64;
- *                    0 = tune: 16, 32, 64 and the most chains, up to 64,
- *                    whose lattice and table both fit in LDS)
+ *   chains_per_wg    chains handled by one workgroup, 1..64 (0 = tune: 16,
+ *                    32, 64 and the most chains, up to 64, whose lattice and
+ *                    table both fit in LDS); a count whose arrays do not fit
+ *                    in the requested placement makes mucaInit fail
  *   rng_mode         0 = tune, 1 = walker draws its own numbers,
  *                    2, 3, 4 = one, two or three helper waves of the
  *                    workgroup draw them (and, for the fast walkers, form
@@ -132,8 +133,7 @@ typedef struct {
     int64_t total;            /* sum of H = chains * recorded sweeps */
 } muca_iter_stats;
 
-/* Selected launch configuration of one problem (after tuning; chains_per_wg
- * is 1..64 and need not be one of the sizes a caller may request). */
+/* Selected launch configuration of one problem (after tuning). */
 typedef struct {
     int32_t chains_per_wg, rng_mode, spin_placement, table_placement;
     int32_t lds_bytes, n_workgroups;

@@ -153,8 +153,7 @@ muca_status validate(const muca_problem *pr, int32_t n, const muca_options *o) {
     }
     if (o) {
         const int cw = o->chains_per_wg;
-        if (!(cw == 0 || cw == 4 || cw == 8 || cw == 16 || cw == 32 || cw == 64))
-            return fail(nullptr, MUCA_EINVAL, "chains_per_wg must be 0, 4, 8, 16, 32 or 64");
+        if (cw < 0 || cw > 64) return fail(nullptr, MUCA_EINVAL, "chains_per_wg must be 0 (tune) or 1..64");
         if (o->rng_mode < 0 || o->rng_mode > 4) return fail(nullptr, MUCA_EINVAL, "rng_mode must be 0..4");
         if (o->spin_placement < 0 || o->spin_placement > 2 || o->table_placement < 0 || o->table_placement > 2)
             return fail(nullptr, MUCA_EINVAL, "placements must be 0..2");

@@ -381,19 +381,26 @@ def test_packed_l64_walker_bit_exact(chains, cw):
 
 
 @pytest.mark.parametrize("rng_mode", [2, 4], ids=["one-producer", "three-producers"])
-@pytest.mark.parametrize("prob,n_sweeps", [(Problem(ISING, 16, 40, 51), 3000), (Problem(POTTS, 16, 40, 52, q=8), 3000),
-                                           (Problem(ISING_MAG, 16, 40, 53, beta=0.66), 3000),
-                                           (Problem(POTTS, 24, 30, 54, q=8), 1500), (Problem(ISING, 64, 20, 55), 600)],
-                         ids=["isingL16", "pottsL16", "magL16", "pottsL24", "isingL64"])
-def test_fast_walkers_long_launch_bit_exact(prob, n_sweeps, rng_mode):
+@pytest.mark.parametrize("prob,n_sweeps,cw", [(Problem(ISING, 16, 40, 51), 3000, 16),
+                                              (Problem(POTTS, 16, 40, 52, q=8), 3000, 16),
+                                              (Problem(ISING_MAG, 16, 40, 53, beta=0.66), 3000, 16),
+                                              (Problem(POTTS, 24, 30, 54, q=8), 1500, 16),
+                                              (Problem(POTTS, 32, 60, 57, q=8), 600, 47),
+                                              (Problem(ISING, 64, 20, 55), 600, 16),
+                                              (Problem(ISING, 64, 80, 56), 300, 64)],
+                         ids=["isingL16", "pottsL16", "magL16", "pottsL24", "pottsL32-wide", "isingL64",
+                              "isingL64-packed"])
+def test_fast_walkers_long_launch_bit_exact(prob, n_sweeps, cw, rng_mode):
     """One long launch of each fast walker with non-trivial weights: thousands
     of chunk hand-offs between the producer waves (which read the lattice one or
     two chunks ahead of the walker) and the walker, with one or three producer
-    waves.  L = 16 has four chunks per sweep, the fewest the walkers allow.
+    waves.  L = 16 has four chunks per sweep, the fewest the walkers allow; the
+    wide cases run the Potts walker with its small chunks and the packed Ising
+    L = 64 walker (each next to a narrow work item for the remaining chains).
     Trajectories, per-chain histograms and energies equal the oracle's."""
     pm = _pm()
-    print("case", prob, n_sweeps, rng_mode, flush=True)
-    with pm.Muca([prob], rng_mode=rng_mode, chains_per_wg=16, spin_placement=1, table_placement=1) as ctx:
+    print("case", prob, n_sweeps, cw, rng_mode, flush=True)
+    with pm.Muca([prob], rng_mode=rng_mode, chains_per_wg=cw, spin_placement=1, table_placement=1) as ctx:
         info = ctx.launch_info()
         print("launch", info, flush=True)
         assert info["fast_walker"] == 1

@@ -54,9 +54,11 @@ def test_workspace_size_and_validation():
     assert _status([P(2, 7, 4, beta=0.66)])[0] == -1          # odd L
     assert _status([P(2, 8, 4, beta=-0.1)])[0] == -1          # beta < 0
     assert _status([P(2, 8, 4, beta=float("nan"))])[0] == -1  # beta not a number
-    assert _status([P(0, 8, 4)], chains_per_wg=12)[0] == -1
+    assert _status([P(0, 8, 4)], chains_per_wg=12)[0] == 0
+    assert _status([P(0, 8, 4)], chains_per_wg=65)[0] == -1
     msg = pm.lib().mucaLastError(None).decode()
     assert "chains_per_wg" in msg
+    assert _status([P(0, 8, 4)], chains_per_wg=-1)[0] == -1
 
 
 def test_init_rejects_small_workspace_without_gpu_calls():
