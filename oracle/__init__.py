@@ -328,14 +328,44 @@ def _log_canonical(model: int, L: int, lnW: np.ndarray, cnt: np.ndarray, beta: f
     return ks, a
 
 
-def _two_peaks(model, L, lnW, cnt, beta):
-    """The ordered and disordered peaks and the minimum between them.
+def _best_valley(a: np.ndarray):
+    """Score of each point as the bottom of a double peak: its depth below the
+    lower of the highest values on its two sides (itself included), less the
+    difference of those two highest values.  A balanced double peak scores the
+    depth of its valley; a dip beside a far smaller side scores below zero.
+    Returns the first best point and its score."""
+    left = np.maximum.accumulate(a)
+    right = np.maximum.accumulate(a[::-1])[::-1]
+    score = 2.0 * np.minimum(left, right) - np.maximum(left, right) - a
+    i = int(np.argmax(score))
+    return i, float(score[i])
 
-    Reading: the two peaks are the largest ln P on either side of the mean bin
-    (weights P), the minimum the smallest ln P between the two peaks."""
+
+def _valley_split(model, L, lnW, cnt, beta_lo, beta_hi):
+    """The bin that separates the ordered from the disordered peak.
+
+    Reading: the two peaks are separated at the valley of the reweighted
+    histogram, taken where the histogram is most clearly double-peaked: over 65
+    equally spaced beta in the bracket, the best-scoring valley (its depth less
+    the height difference of its two sides) at the beta where that score is
+    highest.  A split fixed in k makes the peak-height difference below a
+    continuous, increasing function of beta."""
+    best, split = 0.0, None
+    for i in range(65):
+        b = beta_lo + (beta_hi - beta_lo) * i / 64.0
+        ks, a = _log_canonical(model, L, lnW, cnt, b)
+        j, score = _best_valley(a)
+        if score > best:
+            best, split = score, int(ks[j])
+    if split is None:
+        raise ValueError("no two peaks")
+    return split
+
+
+def _two_peaks(model, L, lnW, cnt, beta, split):
+    """The ordered and disordered peaks (the largest ln P at k <= split and at
+    k > split) and the smallest ln P between them."""
     ks, a = _log_canonical(model, L, lnW, cnt, beta)
-    p = np.exp(a - a.max())
-    split = int(np.floor((p * ks).sum() / p.sum()))
     low, high = ks <= split, ks > split
     if not low.any() or not high.any():
         raise ValueError("no two peaks")
@@ -350,14 +380,16 @@ def interface_tension(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: flo
 
     Step 1: find the inverse temperature at which the histogram reweighted to
     the canonical ensemble has two equally high peaks (bisection on the
-    difference of the two log peak heights, which grows with beta because the
-    ordered peak has the lower energy).  Step 2: sigma_od = ln(P_max/P_min) /
+    difference of the two log peak heights on either side of the valley bin,
+    which grows with beta because the ordered side has the lower energies).  Step 2: sigma_od = ln(P_max/P_min) /
     (2L) there, with P_max the common peak height.  Returns (beta, sigma,
     (k_ordered, k_min, k_disordered))."""
-    def gap(beta):
-        _, (ao, _, ad) = _two_peaks(model, L, lnW, cnt, beta)
-        return ao - ad
     lo, hi = float(beta_lo), float(beta_hi)
+    split = _valley_split(model, L, lnW, cnt, lo, hi)
+
+    def gap(beta):
+        _, (ao, _, ad) = _two_peaks(model, L, lnW, cnt, beta, split)
+        return ao - ad
     if not (gap(lo) < 0.0 < gap(hi)):
         raise ValueError("peak heights do not cross in the bracket")
     for _ in range(200):
@@ -369,7 +401,7 @@ def interface_tension(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: flo
         else:
             hi = mid
     beta = 0.5 * (lo + hi)
-    ks, (ao, am, ad) = _two_peaks(model, L, lnW, cnt, beta)
+    ks, (ao, am, ad) = _two_peaks(model, L, lnW, cnt, beta, split)
     if not ks[0] < ks[1] < ks[2]:
         raise ValueError("no minimum between the peaks: one peak only")
     return beta, (0.5 * (ao + ad) - am) / (2.0 * L), ks

@@ -628,35 +628,77 @@ struct PeakSplit {
     double ao = 0, am = 0, ad = 0;
 };
 
-bool split_peaks(const int64_t *cnt, const double *lnW, const double *E, int nb, double beta, PeakSplit &ps) {
-    std::vector<double> a(nb, 0.0);
-    double A = -HUGE_VAL;
+// a_k = ln cnt_k - lnW_k - beta E_k (the log canonical probability at beta up
+// to a constant, Eq. 2) over the bins with data, in increasing k.
+void log_canonical(const int64_t *cnt, const double *lnW, const double *E, int nb, double beta,
+                   std::vector<int> &ks, std::vector<double> &a) {
+    ks.clear();
+    a.clear();
     for (int k = 0; k < nb; ++k)
         if (cnt[k] > 0) {
-            a[k] = std::log((double)cnt[k]) - lnW[k] - beta * E[k];
-            if (a[k] > A) A = a[k];
+            ks.push_back(k);
+            a.push_back(std::log((double)cnt[k]) - lnW[k] - beta * E[k]);
         }
-    if (A == -HUGE_VAL) return false;
-    double z = 0.0, zk = 0.0;
-    for (int k = 0; k < nb; ++k)
-        if (cnt[k] > 0) {
-            const double w = std::exp(a[k] - A);
-            z += w;
-            zk += w * (double)k;
+}
+
+// The bin separating the ordered from the disordered peak.  A point scores as
+// the bottom of a double peak with its depth below the lower of the highest
+// values on its two sides (itself included), less the difference of those two
+// highest values: a balanced double peak scores the depth of its valley, a dip
+// beside a far smaller side (noise in a tail) scores below zero.  The split is
+// the best point at the beta of the bracket where the best score is highest,
+// over 65 equally spaced beta.  Fixed in k, it makes the peak-height
+// difference continuous and increasing in beta.  False if no point scores
+// above zero.
+bool valley_split(const int64_t *cnt, const double *lnW, const double *E, int nb, double beta_lo, double beta_hi,
+                  int &split) {
+    std::vector<int> ks;
+    std::vector<double> a, right;
+    double best = 0.0;
+    split = -1;
+    for (int i = 0; i <= 64; ++i) {
+        const double beta = beta_lo + (beta_hi - beta_lo) * i / 64.0;
+        log_canonical(cnt, lnW, E, nb, beta, ks, a);
+        const int n = (int)a.size();
+        if (n == 0) return false;
+        right.assign(n, 0.0);
+        right[n - 1] = a[n - 1];
+        for (int j = n - 2; j >= 0; --j) right[j] = std::max(right[j + 1], a[j]);
+        double left = -HUGE_VAL, smax = -HUGE_VAL;
+        int jmax = -1;
+        for (int j = 0; j < n; ++j) {
+            left = std::max(left, a[j]);
+            const double sc = 2.0 * std::min(left, right[j]) - std::max(left, right[j]) - a[j];
+            if (jmax < 0 || sc > smax) smax = sc, jmax = j;
         }
-    const int split = (int)std::floor(zk / z);
+        if (smax > best) best = smax, split = ks[jmax];
+    }
+    return split >= 0;
+}
+
+// The ordered peak (largest a_k at k <= split), the disordered peak (largest
+// a_k at k > split) and the smallest a_k between them, at beta.
+bool split_peaks(const int64_t *cnt, const double *lnW, const double *E, int nb, double beta, int split,
+                 PeakSplit &ps) {
+    std::vector<int> ks;
+    std::vector<double> a;
+    log_canonical(cnt, lnW, E, nb, beta, ks, a);
     ps = PeakSplit();
-    for (int k = 0; k < nb; ++k) {
-        if (cnt[k] <= 0) continue;
-        if (k <= split) {
-            if (ps.ko < 0 || a[k] > ps.ao) ps.ko = k, ps.ao = a[k];
+    int io = -1, id = -1;
+    for (int j = 0; j < (int)ks.size(); ++j) {
+        if (ks[j] <= split) {
+            if (io < 0 || a[j] > a[io]) io = j;
         } else {
-            if (ps.kd < 0 || a[k] > ps.ad) ps.kd = k, ps.ad = a[k];
+            if (id < 0 || a[j] > a[id]) id = j;
         }
     }
-    if (ps.ko < 0 || ps.kd < 0) return false;
-    for (int k = ps.ko; k <= ps.kd; ++k)
-        if (cnt[k] > 0 && (ps.km < 0 || a[k] < ps.am)) ps.km = k, ps.am = a[k];
+    if (io < 0 || id < 0) return false;
+    int im = io;
+    for (int j = io; j <= id; ++j)
+        if (a[j] < a[im]) im = j;
+    ps.ko = ks[io], ps.ao = a[io];
+    ps.kd = ks[id], ps.ad = a[id];
+    ps.km = ks[im], ps.am = a[im];
     return true;
 }
 
@@ -670,8 +712,12 @@ muca_status equal_height(muca_ctx ctx, int32_t model, int32_t L, const double *l
     if (!(beta_lo < beta_hi)) return fail(ctx, MUCA_EINVAL, "need beta_lo < beta_hi");
     std::vector<double> E(nb);
     for (int k = 0; k < nb; ++k) E[k] = (double)(-2 * N + (model == MUCA_ISING ? 2 * k : k));
+    int split = -1;
+    if (!valley_split(cnt, lnW, E.data(), nb, beta_lo, beta_hi, split))
+        return fail(ctx, MUCA_ESTATE, "histogram has no two peaks");
     PeakSplit lo_ps, hi_ps;
-    if (!split_peaks(cnt, lnW, E.data(), nb, beta_lo, lo_ps) || !split_peaks(cnt, lnW, E.data(), nb, beta_hi, hi_ps))
+    if (!split_peaks(cnt, lnW, E.data(), nb, beta_lo, split, lo_ps) ||
+        !split_peaks(cnt, lnW, E.data(), nb, beta_hi, split, hi_ps))
         return fail(ctx, MUCA_ESTATE, "histogram has no two peaks");
     // the ordered (low-energy) peak gains on the disordered one as beta grows
     if (!(lo_ps.ao - lo_ps.ad < 0.0 && hi_ps.ao - hi_ps.ad > 0.0))
@@ -681,12 +727,12 @@ muca_status equal_height(muca_ctx ctx, int32_t model, int32_t L, const double *l
     for (int it = 0; it < 200; ++it) {
         const double mid = 0.5 * (lo + hi);
         if (!(mid > lo && mid < hi)) break;
-        if (!split_peaks(cnt, lnW, E.data(), nb, mid, ps)) return fail(ctx, MUCA_ESTATE, "lost the two peaks");
+        if (!split_peaks(cnt, lnW, E.data(), nb, mid, split, ps)) return fail(ctx, MUCA_ESTATE, "lost the two peaks");
         if (ps.ao - ps.ad < 0.0) lo = mid;
         else hi = mid;
     }
     const double beta = 0.5 * (lo + hi);
-    if (!split_peaks(cnt, lnW, E.data(), nb, beta, ps)) return fail(ctx, MUCA_ESTATE, "lost the two peaks");
+    if (!split_peaks(cnt, lnW, E.data(), nb, beta, split, ps)) return fail(ctx, MUCA_ESTATE, "lost the two peaks");
     // a single peak splits into two neighbouring "maxima" with no bin between them
     if (!(ps.ko < ps.km && ps.km < ps.kd)) return fail(ctx, MUCA_ESTATE, "histogram has no two peaks");
     *beta_out = beta;

@@ -3,7 +3,8 @@
 Orchestration only (every step runs in libmuca.so).  For each lattice size:
   1. Seed the log-weights with the learned network, if parameters are given,
      or (--chain-seed) with the previous size's converged weights rescaled
-     per site (ln W / N as a function of E / N carries over between sizes).
+     per site (ln W / N as a function of E / N carries over between sizes), or
+     (--weights) with an earlier run's weights for the same size.
   2. Iterate the recursion, with the correction function, until the merged
      histogram is flat; then refine it with a few more iterations.
   3. Re-thermalise, then run production sweeps.
@@ -52,7 +53,7 @@ def rescaled_weights(lnW_prev, L_prev, L):
 def run_size(L, chains, seed, sweeps, cap, refine, n_therm, n_prod, mlp, max_seconds, seed_lnw=None, flat_rule=0):
     prob = Problem(POTTS, L, chains, seed, q=8)
     rec = {"L": L, "chains": chains, "seed": seed, "sweeps_per_iter": sweeps,
-           "weights_seed": "previous size" if seed_lnw is not None else ("learned" if mlp is not None else "zero")}
+           "weights_seed": "given" if seed_lnw is not None else ("learned" if mlp is not None else "zero")}
     t0 = time.time()
     rec["flat_rule"] = "paper: [<H>/2, 2<H>]" if flat_rule == 1 else "min/max >= 0.5"
     with pm.Muca([prob], correction=1, flat_rule=flat_rule) as ctx:
@@ -107,6 +108,8 @@ def main():
     ap.add_argument("--params", default="", help="learned network parameters (mlp_params.npy) for the seed")
     ap.add_argument("--seed-weights", default="",
                     help="log_weights.npz of an earlier run: seed the first size from its largest smaller L")
+    ap.add_argument("--weights", default="",
+                    help="log_weights.npz of an earlier run: a size with an entry (L<size>) starts from those weights")
     ap.add_argument("--flat-rule", type=int, default=0, choices=[0, 1],
                     help="0: every reachable bin visited and min/max >= 0.5; 1: the paper's [<H>/2, 2<H>]")
     ap.add_argument("--chain-seed", action="store_true",
@@ -130,9 +133,12 @@ def main():
         if not smaller:
             raise SystemExit(f"{args.seed_weights} holds no size below L={sizes[0]}")
         prev = (smaller[-1], saved[f"L{smaller[-1]}"])
+    own = np.load(args.weights) if args.weights else None
     for L in sizes:
         use_prev = prev is not None and (args.chain_seed or (args.seed_weights and L == sizes[0]))
         seed_lnw = rescaled_weights(prev[1], prev[0], L) if use_prev else None
+        if own is not None and f"L{L}" in own.files:
+            seed_lnw = np.asarray(own[f"L{L}"], np.float64)
         rec, lnP, lnW = run_size(L, args.chains, args.seed, args.sweeps, args.cap, args.refine, args.therm,
                                  args.prod, mlp, args.max_seconds, seed_lnw, args.flat_rule)
         results.append(rec)

@@ -40,9 +40,20 @@ def test_library_equal_height_matches_oracle(tilt):
 def test_library_equal_height_errors():
     import paper_1212_3975_amd as pm
     L = 8
-    lnW, cnt = double_well(POTTS, L, 30, 40, 1.0, B0_POTTS8)
-    with pytest.raises(pm.MucaError, match="do not cross"):
+    N = L * L
+    E = oracle.energies(POTTS, L)
+    k = np.arange(2 * N + 1)
+    # a double well with steep flanks over the whole range; in a bracket above
+    # its equal-height beta the peaks neither cross nor show a balanced valley
+    k1, period, h = 30, 40, 1.0
+    f = h * np.cos(2.0 * np.pi * (k - k1) / period)
+    f = np.where(k < k1, h - 0.5 * (k1 - k), np.where(k > k1 + period, h - 0.5 * (k - k1 - period), f))
+    lnW, cnt = -(B0_POTTS8 * E + f), np.ones(2 * N + 1, np.int64)
+    with pytest.raises(pm.MucaError, match="do not cross|no two peaks"):
         pm.equal_height(POTTS, L, lnW, cnt, B0_POTTS8 + 0.05, B0_POTTS8 + 0.2)
+    one = -(B0_POTTS8 * E - 0.01 * (k - 60.0) ** 2)   # one peak
+    with pytest.raises(pm.MucaError, match="no two peaks"):
+        pm.equal_height(POTTS, L, one, cnt, B0_POTTS8 - 0.2, B0_POTTS8 + 0.2)
     with pytest.raises(pm.MucaError, match="2N\\+1"):
         pm.equal_height(POTTS, L, lnW[:-1], cnt[:-1], 1.0, 1.5)
     with pytest.raises(pm.MucaError):
@@ -69,3 +80,18 @@ def test_library_equal_height_refuses_the_magnetization_axis():
     lnW, cnt = double_well(POTTS, L, 30, 40, 1.0, B0_POTTS8)
     with pytest.raises(pm.MucaError):
         pm.equal_height(pm.ISING_MAG, L, lnW, cnt, 1.3, 1.4)
+
+
+@pytest.mark.parametrize("lo,hi", [(-0.03, 0.15), (-0.15, 0.03), (-0.2, 0.2)])
+def test_library_equal_height_wide_bracket_matches_oracle(lo, hi):
+    """Brackets where one phase dominates over most of the range: the split at
+    the valley keeps both sides on the true crossing, clean and noisy."""
+    rng = np.random.default_rng(13)
+    L = 12
+    lnW, cnt = double_well(POTTS, L, 60, 80, 1.7, B0_POTTS8)
+    got = _lib_vs_oracle(POTTS, L, lnW, cnt, B0_POTTS8 + lo, B0_POTTS8 + hi)
+    assert got["beta"] == pytest.approx(B0_POTTS8, abs=1e-12)
+    noisy = rng.poisson(np.where(cnt > 0, 400.0, 0.0)).astype(np.int64)
+    noisy[(cnt > 0) & (noisy == 0)] = 1
+    got = _lib_vs_oracle(POTTS, L, lnW, noisy, B0_POTTS8 + lo, B0_POTTS8 + hi)
+    assert abs(got["beta"] - B0_POTTS8) < 2e-3

@@ -8,11 +8,13 @@ f(k) + (b* - beta) E_k.  At beta = b*, it has two equal peaks of height h, at
 k1 and k1 + P, and the minimum -h halfway between them.  So the equal-height
 beta is b*, and sigma_od = (h - (-h)) / (2L) = h / L.  A wrong sign of
 beta E, a dropped ln cnt, a wrong factor in 1/(2L) or an unequal-height beta
-each move one of these values.  The bracket of beta is kept narrow enough that
-the tilt (beta - b*) E across the two peaks stays below the barrier 2h; wider,
-the tilt piles the probability onto the edges of the window and makes new
-crossings, which a real multicanonical histogram (covering every bin) does not
-have.
+each move one of these values.
+
+Wide brackets are pinned too: there the tilt (beta - b*) E makes one phase
+dominate at most beta of the bracket, so a split between the peaks that moves
+with beta (at the mean of the reweighted distribution) lands inside the
+dominant peak and finds a false crossing.  The split at the deepest valley,
+fixed in k, does not.
 """
 import math
 
@@ -99,6 +101,25 @@ def test_equal_height_refuses_one_peak_and_a_bad_bracket():
     cnt = np.ones(2 * N + 1, np.int64)
     with pytest.raises(ValueError):
         oracle.interface_tension(POTTS, L, -ln_omega, cnt, B0_POTTS8 - 0.2, B0_POTTS8 + 0.2)
-    lnW, cnt = double_well(POTTS, L, 30, 40, 1.0, B0_POTTS8)
-    with pytest.raises(ValueError):   # both ends above the equal-height beta
+    # both ends above the equal-height beta, for a double well in steep tails
+    # over the whole range (as in a sampled histogram, whose edges lie far
+    # below its peaks, so that no tilt in the bracket makes an edge a peak)
+    k1, period, h = 30, 40, 1.0
+    f = h * np.cos(2.0 * np.pi * (k - k1) / period)
+    f = np.where(k < k1, h - 0.5 * (k1 - k), np.where(k > k1 + period, h - 0.5 * (k - k1 - period), f))
+    lnW = -(B0_POTTS8 * E + f)
+    assert oracle.interface_tension(POTTS, L, lnW, cnt, B0_POTTS8 - 0.2, B0_POTTS8 + 0.2)[0] == \
+        pytest.approx(B0_POTTS8, abs=1e-12)
+    with pytest.raises(ValueError):
         oracle.interface_tension(POTTS, L, lnW, cnt, B0_POTTS8 + 0.05, B0_POTTS8 + 0.2)
+
+
+@pytest.mark.parametrize("model,L,k1,period,lo,hi", [(POTTS, 8, 30, 40, -0.2, 0.2), (POTTS, 12, 60, 80, -0.03, 0.15),
+                                                     (POTTS, 12, 60, 80, -0.15, 0.03), (ISING, 8, 20, 30, -0.1, 0.3)])
+def test_equal_height_with_a_wide_bracket(model, L, k1, period, lo, hi):
+    h = 1.7
+    lnW, cnt = double_well(model, L, k1, period, h, B0_POTTS8)
+    beta, sigma, ks = oracle.interface_tension(model, L, lnW, cnt, B0_POTTS8 + lo, B0_POTTS8 + hi)
+    assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
+    assert sigma == pytest.approx(h / L, rel=1e-12)
+    assert ks == (k1, k1 + period // 2, k1 + period)
