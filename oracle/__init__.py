@@ -330,13 +330,18 @@ def _log_canonical(model: int, L: int, lnW: np.ndarray, cnt: np.ndarray, beta: f
 
 def _best_valley(a: np.ndarray):
     """Score of each point as the bottom of a double peak: its depth below the
-    lower of the highest values on its two sides (itself included), less the
-    difference of those two highest values.  A balanced double peak scores the
-    depth of its valley; a dip beside a far smaller side scores below zero.
-    Returns the first best point and its score."""
+    lower of the highest values on its two sides (itself included), less
+    |ln(M_left / M_right)|, M the probability (sum of e^a) on each side, the
+    point included in both.  The two phases of a double peak carry comparable
+    probability; an isolated bin at an edge or a dip in a tail does not, and
+    scores below zero.  Returns the first best point and its score."""
     left = np.maximum.accumulate(a)
     right = np.maximum.accumulate(a[::-1])[::-1]
-    score = 2.0 * np.minimum(left, right) - np.maximum(left, right) - a
+    w = np.exp(a - a.max())
+    m_left = np.cumsum(w)
+    m_right = np.cumsum(w[::-1])[::-1]
+    with np.errstate(divide="ignore"):   # a side whose e^a underflows scores -inf
+        score = np.minimum(left, right) - a - np.abs(np.log(m_left) - np.log(m_right))
     i = int(np.argmax(score))
     return i, float(score[i])
 
@@ -347,8 +352,8 @@ def _valley_split(model, L, lnW, cnt, beta_lo, beta_hi):
     Reading: the two peaks are separated at the valley of the reweighted
     histogram, taken where the histogram is most clearly double-peaked: over 65
     equally spaced beta in the bracket, the best-scoring valley (its depth less
-    the height difference of its two sides) at the beta where that score is
-    highest.  A split fixed in k makes the peak-height difference below a
+    the log ratio of the probabilities on its two sides) at the beta where
+    that score is highest.  A split fixed in k makes the peak-height difference below a
     continuous, increasing function of beta."""
     best, split = 0.0, None
     for i in range(65):

@@ -643,17 +643,18 @@ void log_canonical(const int64_t *cnt, const double *lnW, const double *E, int n
 
 // The bin separating the ordered from the disordered peak.  A point scores as
 // the bottom of a double peak with its depth below the lower of the highest
-// values on its two sides (itself included), less the difference of those two
-// highest values: a balanced double peak scores the depth of its valley, a dip
-// beside a far smaller side (noise in a tail) scores below zero.  The split is
-// the best point at the beta of the bracket where the best score is highest,
-// over 65 equally spaced beta.  Fixed in k, it makes the peak-height
+// values on its two sides (itself included), less |ln(M_left / M_right)|, M
+// the probability (sum of e^a) on each side, the point counted on both.  The
+// two phases of a double peak carry comparable probability; an isolated bin
+// at an edge or a dip in a tail does not, and scores below zero.  The split
+// is the best point at the beta of the bracket where the best score is
+// highest, over 65 equally spaced beta.  Fixed in k, it makes the peak-height
 // difference continuous and increasing in beta.  False if no point scores
 // above zero.
 bool valley_split(const int64_t *cnt, const double *lnW, const double *E, int nb, double beta_lo, double beta_hi,
                   int &split) {
     std::vector<int> ks;
-    std::vector<double> a, right;
+    std::vector<double> a, right, mright;
     double best = 0.0;
     split = -1;
     for (int i = 0; i <= 64; ++i) {
@@ -661,14 +662,22 @@ bool valley_split(const int64_t *cnt, const double *lnW, const double *E, int nb
         log_canonical(cnt, lnW, E, nb, beta, ks, a);
         const int n = (int)a.size();
         if (n == 0) return false;
+        double A = a[0];
+        for (int j = 1; j < n; ++j) A = std::max(A, a[j]);
         right.assign(n, 0.0);
+        mright.assign(n, 0.0);
         right[n - 1] = a[n - 1];
-        for (int j = n - 2; j >= 0; --j) right[j] = std::max(right[j + 1], a[j]);
-        double left = -HUGE_VAL, smax = -HUGE_VAL;
+        mright[n - 1] = std::exp(a[n - 1] - A);
+        for (int j = n - 2; j >= 0; --j) {
+            right[j] = std::max(right[j + 1], a[j]);
+            mright[j] = mright[j + 1] + std::exp(a[j] - A);
+        }
+        double left = -HUGE_VAL, mleft = 0.0, smax = -HUGE_VAL;
         int jmax = -1;
         for (int j = 0; j < n; ++j) {
             left = std::max(left, a[j]);
-            const double sc = 2.0 * std::min(left, right[j]) - std::max(left, right[j]) - a[j];
+            mleft += std::exp(a[j] - A);
+            const double sc = std::min(left, right[j]) - a[j] - std::fabs(std::log(mleft) - std::log(mright[j]));
             if (jmax < 0 || sc > smax) smax = sc, jmax = j;
         }
         if (smax > best) best = smax, split = ks[jmax];

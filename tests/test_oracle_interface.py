@@ -123,3 +123,25 @@ def test_equal_height_with_a_wide_bracket(model, L, k1, period, lo, hi):
     assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
     assert sigma == pytest.approx(h / L, rel=1e-12)
     assert ks == (k1, k1 + period // 2, k1 + period)
+
+
+def test_equal_height_ignores_an_isolated_ground_state():
+    """The ground state sits alone at k = 0 (k = 1..3 cannot occur) below a
+    tail that rises into the ordered peak, as in a sampled Potts histogram.
+    Under the tilt of the bracket's upper end it forms a small separate
+    maximum; carrying almost no probability, it does not take the split."""
+    L = 8
+    N = L * L
+    E = oracle.energies(POTTS, L)
+    k = np.arange(2 * N + 1)
+    k1, period, h = 30, 40, 1.0
+    f = h * np.cos(2.0 * np.pi * (k - k1) / period)
+    f = np.where(k < k1, h - 0.3 * (k1 - k), np.where(k > k1 + period, h - 0.3 * (k - k1 - period), f))
+    f[0] = f[4] - 2.0
+    cnt = np.ones(2 * N + 1, np.int64)
+    cnt[1:4] = 0
+    lnW = -(B0_POTTS8 * E + f)
+    beta, sigma, ks = oracle.interface_tension(POTTS, L, lnW, cnt, B0_POTTS8 - 0.05, B0_POTTS8 + 0.05)
+    assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
+    assert sigma == pytest.approx(h / L, rel=1e-12)
+    assert ks == (k1, k1 + period // 2, k1 + period)
