@@ -191,18 +191,23 @@ muca_status mucaClearProduction(muca_ctx ctx);
 
 /* Order-disorder interface tension from a reweighted energy histogram
  * (Sec. 5, Eq. 9): find the inverse temperature beta_eqh at which the
- * histogram reweighted to the canonical ensemble shows two equally high
- * peaks, and return sigma_od = ln(P_max / P_min) / (2L) there.
+ * histogram reweighted to the canonical ensemble has its two peaks at the
+ * same height, and return sigma_od = ln(P_max / P_min) / (2L) there.
  *
  * At beta, bin k with cnt[k] > 0 carries a_k = ln cnt[k] - lnW[k] - beta E_k
  * (E_k as in the conventions above; the log of the canonical probability up
- * to a constant; bins with cnt[k] = 0 are left out).  Peaks: the maxima of a
- * over k <= floor(kbar) (ordered) and over k > floor(kbar) (disordered), kbar
- * being the bin index averaged with weights e^{a_k}; minimum: the smallest a_k
- * between the two peaks (first index on ties).  beta_eqh is found by
- * bisection of a(ordered peak) - a(disordered peak), which must be < 0 at
- * beta_lo and > 0 at beta_hi; ln(P_max/P_min) uses the mean of the two peak
- * heights.  Host computation in IEEE double with the C library's log/exp.
+ * to a constant; bins with cnt[k] = 0 are left out).  The peaks are split at
+ * the histogram's valley, a bin fixed for the whole search: over 65 equally
+ * spaced beta in [beta_lo, beta_hi], each bin scores its depth below the
+ * lower of the highest a on its two sides less |ln(M_left / M_right)| (M the
+ * sum of e^{a} on each side, the bin on both), and the split is the best bin
+ * at the beta with the highest score.  Peaks: the maxima of a over k <= split
+ * (ordered) and over k > split (disordered); minimum: the smallest a_k between
+ * them (first index on ties).  beta_eqh is found by bisection of
+ * a(ordered peak) - a(disordered peak), which grows with beta and must be < 0
+ * at beta_lo and > 0 at beta_hi; ln(P_max/P_min) uses the mean of the two
+ * peak heights.  Host computation in IEEE double with the C library's
+ * log/exp.
  *
  *   model, L     MUCA_ISING or MUCA_POTTS and the lattice side; n_bins = 2N+1
  *   lnW, cnt     host arrays of n_bins (log-weights of the production run and
@@ -212,8 +217,9 @@ muca_status mucaClearProduction(muca_ctx ctx);
  *   lnP          double[n_bins] or NULL: the normalised log-probabilities at
  *                beta_eqh (-HUGE_VAL where cnt = 0)
  * Returns MUCA_EINVAL for bad arguments and MUCA_ESTATE when the histogram has
- * no two peaks (at beta_eqh no bin lies strictly between them) or their
- * heights do not cross inside [beta_lo, beta_hi].
+ * no two peaks (no bin of any beta in the bracket scores above zero, or at
+ * beta_eqh no bin lies strictly between the peaks) or their heights do not
+ * cross inside [beta_lo, beta_hi].
  * Needs no GPU and no context (errors: mucaLastError(NULL)). */
 muca_status mucaEqualHeight(int32_t model, int32_t L, const double *lnW, const int64_t *cnt, int32_t n_bins,
                             double beta_lo, double beta_hi, double *beta_eqh, double *sigma_od, int32_t *k_peaks,

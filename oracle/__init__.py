@@ -384,7 +384,7 @@ def interface_tension(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: flo
     """Order-disorder interface tension, Eq. (9), Sec. 5.
 
     Step 1: find the inverse temperature at which the histogram reweighted to
-    the canonical ensemble has two equally high peaks (bisection on the
+    the canonical ensemble has its two peaks at the same height (bisection on the
     difference of the two log peak heights on either side of the valley bin,
     which grows with beta because the ordered side has the lower energies).  Step 2: sigma_od = ln(P_max/P_min) /
     (2L) there, with P_max the common peak height.  Returns (beta, sigma,
