@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from oracle import POTTS
-from test_oracle_interface import B0_POTTS8, double_well
+from test_oracle_interface import B0_POTTS8, double_well, noisy_tail_well
 
 
 def _lib_vs_oracle(model, L, lnW, cnt, blo, bhi):
@@ -95,3 +95,9 @@ def test_library_equal_height_wide_bracket_matches_oracle(lo, hi):
     noisy[(cnt > 0) & (noisy == 0)] = 1
     got = _lib_vs_oracle(POTTS, L, lnW, noisy, B0_POTTS8 + lo, B0_POTTS8 + hi)
     assert abs(got["beta"] - B0_POTTS8) < 2e-3
+
+
+def test_library_equal_height_sparse_tail_matches_oracle():
+    lnW, cnt = noisy_tail_well()
+    got = _lib_vs_oracle(POTTS, 8, lnW, cnt, B0_POTTS8 - 0.05, B0_POTTS8 + 0.05)
+    assert got["k_peaks"] == (30, 50, 70)

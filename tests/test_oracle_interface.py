@@ -13,8 +13,9 @@ each move one of these values.
 Wide brackets are pinned too: there the tilt (beta - b*) E makes one phase
 dominate at most beta of the bracket, so a split between the peaks that moves
 with beta (at the mean of the reweighted distribution) lands inside the
-dominant peak and finds a false crossing.  The split at the deepest valley,
-fixed in k, does not.
+dominant peak and finds a false crossing.  The split at the valley, fixed in
+k, does not.  Nor does a dip in a sparsely sampled tail or a lone ground-state
+bin take the split: the two phases carry comparable probability, they do not.
 """
 import math
 
@@ -73,8 +74,8 @@ def test_equal_height_uses_the_counts():
 
 def test_equal_height_with_a_long_disordered_tail():
     # Potts-like asymmetry: a long declining tail on the high-energy side puts
-    # the middle of the sampled range beyond both peaks; the split at the mean
-    # of the reweighted distribution still falls between them
+    # the middle of the sampled range beyond both peaks; the valley split
+    # still falls between them
     L, k1, period, h, tail = 12, 60, 80, 1.9, 100
     N = L * L
     E = oracle.energies(POTTS, L)
@@ -145,3 +146,29 @@ def test_equal_height_ignores_an_isolated_ground_state():
     assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
     assert sigma == pytest.approx(h / L, rel=1e-12)
     assert ks == (k1, k1 + period // 2, k1 + period)
+
+
+def noisy_tail_well(L=8, k1=30, period=40, h=0.5, slope=0.19, dip=5.0):
+    """A shallow double well (valley depth 2h, as for a small Potts lattice)
+    whose low-energy tail, sampled sparsely, has one bin far below its
+    neighbours; the ground state sits alone at k = 0 (k = 1..3 cannot occur)."""
+    N = L * L
+    E = oracle.energies(POTTS, L)
+    k = np.arange(2 * N + 1)
+    f = h * np.cos(2.0 * np.pi * (k - k1) / period)
+    f = np.where(k < k1, h - slope * (k1 - k), np.where(k > k1 + period, h - 0.3 * (k - k1 - period), f))
+    f[9] -= dip
+    cnt = np.ones(2 * N + 1, np.int64)
+    cnt[1:4] = 0
+    return -(B0_POTTS8 * E + f), cnt
+
+
+def test_equal_height_ignores_a_dip_in_a_sparse_tail():
+    """Tilted to the bracket's upper end, the dip is deeper than the phase
+    valley and its two sides differ little in height, but the tail side holds
+    little probability: the split stays at the phase valley."""
+    lnW, cnt = noisy_tail_well()
+    beta, sigma, ks = oracle.interface_tension(POTTS, 8, lnW, cnt, B0_POTTS8 - 0.05, B0_POTTS8 + 0.05)
+    assert beta == pytest.approx(B0_POTTS8, abs=1e-12)
+    assert sigma == pytest.approx(0.5 / 8, rel=1e-12)
+    assert ks == (30, 50, 70)
