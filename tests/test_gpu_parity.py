@@ -386,10 +386,12 @@ def test_packed_l64_walker_bit_exact(chains, cw):
                                               (Problem(ISING_MAG, 16, 40, 53, beta=0.66), 3000, 16),
                                               (Problem(POTTS, 24, 30, 54, q=8), 1500, 16),
                                               (Problem(POTTS, 32, 60, 57, q=8), 600, 47),
+                                              (Problem(POTTS, 16, 80, 58, q=8), 1500, 64),
+                                              (Problem(POTTS, 24, 80, 59, q=8), 800, 64),
                                               (Problem(ISING, 64, 20, 55), 600, 16),
                                               (Problem(ISING, 64, 80, 56), 300, 64)],
-                         ids=["isingL16", "pottsL16", "magL16", "pottsL24", "pottsL32-wide", "isingL64",
-                              "isingL64-packed"])
+                         ids=["isingL16", "pottsL16", "magL16", "pottsL24", "pottsL32-wide", "pottsL16-wide",
+                              "pottsL24-wide", "isingL64", "isingL64-packed"])
 def test_fast_walkers_long_launch_bit_exact(prob, n_sweeps, cw, rng_mode):
     """One long launch of each fast walker with non-trivial weights: thousands
     of chunk hand-offs between the producer waves (which read the lattice one or
