@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 import paper_1212_3975_amd as pm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -68,3 +70,13 @@ def test_init_rejects_small_workspace_without_gpu_calls():
     rc = pm.lib().mucaInit(ctypes.byref(ctx), probs, 1, ctypes.byref(o), ctypes.c_void_p(256), 16, None)
     assert rc == -2 and not ctx.value
     assert "workspace" in pm.lib().mucaLastError(None).decode()
+
+
+def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
+    """No fallback: without libmuca.so every entry point of the binding raises."""
+    monkeypatch.setattr(pm, "_lib", None)
+    monkeypatch.setattr(pm, "LIB_PATH", str(tmp_path / "libmuca.so"))
+    with pytest.raises(pm.MucaError, match="missing"):
+        pm.lib()
+    with pytest.raises(pm.MucaError, match="missing"):
+        _status([P(0, 8, 4)])
