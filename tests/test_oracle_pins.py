@@ -47,6 +47,16 @@ def test_philox_matches_independent_implementation(tmp_path_factory):
         assert got == ref, (c, got, ref)
 
 
+def test_philox_known_answers():
+    """The generator's published known-answer values (tests/golden)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(v, 16) for v in r]
+        assert [int(v) for v in oracle.philox(w[0:4], w[4:6])] == w[6:10], r
+
+
 def test_philox_output_bits_are_balanced():
     """Every output bit of consecutive counters is 1 about half the time."""
     words = np.array([oracle.philox((i, 7, 3, 0), (1, 0)) for i in range(4096)], np.uint32).ravel()
