@@ -159,6 +159,56 @@ def test_table_monotone_in_weight_difference():
     assert vals[0] == 0 and vals[-1] == 0xFFFFFFFF
 
 
+# ------------------------------------------------------------------ flatness
+
+def test_flatness_on_hand_made_histograms():
+    """Hand-made histograms over a mask with unreachable holes.  Default rule:
+    every reachable bin visited and min/max >= 1/2 (equality counts as flat).
+    The paper's rule (Sec. 3): every reachable entry within [avg/2, 2 avg].
+    Unreachable bins never count, visited or not."""
+    mask = np.array([1, 0, 1, 1, 1, 0, 1, 1], bool)
+    h = np.array([10, 0, 5, 7, 9, 0, 6, 10], np.int64)       # min/max = 5/10 exactly
+    f = oracle.flatness(h, mask)
+    assert f.covered and f.flat and f.min_over_max == 0.5
+    assert (f.k_lo, f.k_hi, f.visited, f.reachable) == (0, 7, 6, 6)
+    assert f.min_over_avg == pytest.approx(5 / 7.833333333333333)
+    h2 = h.copy()
+    h2[2] = 4                                                 # 4/10 < 1/2
+    assert oracle.flatness(h2, mask).covered and not oracle.flatness(h2, mask).flat
+    h3 = h.copy()
+    h3[6] = 0                                                 # a reachable bin never visited
+    f3 = oracle.flatness(h3, mask)
+    assert not f3.covered and not f3.flat and f3.visited == 5
+    assert not oracle.flatness(h3, mask, rule=1).flat
+    h4 = h.copy()
+    h4[5] = 1000                                              # unreachable bins are ignored
+    assert oracle.flatness(h4, mask).flat and oracle.flatness(h4, mask).min_over_max == 0.5
+    # the paper's rule: avg = 2, min = avg/2 and max = 3 <= 2 avg: flat by it,
+    # not by min/max = 1/3; min below avg/2 or max above 2 avg is not flat
+    m = np.ones(10, bool)
+    p = np.array([1, 2, 2, 2, 2, 2, 2, 2, 2, 3], np.int64)
+    assert oracle.flatness(p, m, rule=1).flat and not oracle.flatness(p, m).flat
+    assert not oracle.flatness(np.array([1, 3, 3, 3, 3, 3, 3, 3, 3, 3]), m, rule=1).flat   # 1 < 2.8/2
+    assert not oracle.flatness(np.array([9, 2, 2, 2, 2, 2, 2, 2, 2, 2]), m, rule=1).flat   # 9 > 2 * 2.7
+
+
+def test_flatness_rules_are_scale_free_and_nested():
+    """Neither rule changes when every count is multiplied by a constant, and
+    min/max >= 1/2 implies the paper's rule (min >= max/2 >= avg/2 and
+    max <= 2 min <= 2 avg)."""
+    rng = np.random.default_rng(8)
+    mask = oracle.reachable(ISING, 2, 8)
+    n_flat = 0
+    for _ in range(400):
+        h = np.where(mask, rng.integers(1, 40, mask.size) + rng.integers(30, 60), 0).astype(np.int64)
+        for rule in (0, 1):
+            assert oracle.flatness(h, mask, rule=rule).flat == oracle.flatness(7 * h, mask, rule=rule).flat
+        if oracle.flatness(h, mask).flat:
+            n_flat += 1
+            assert oracle.flatness(h, mask, rule=1).flat
+    assert 0 < n_flat < 400
+
+
 # ------------------------------------------------------------------ sampler
 
 @pytest.mark.parametrize("model,L,q", [(ISING, 4, 2), (ISING, 6, 2), (POTTS, 3, 8), (POTTS, 5, 8)])
