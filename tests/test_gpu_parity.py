@@ -254,6 +254,35 @@ def test_correction_function_bit_exact(prob):
             assert np.array_equal(ctx.spins(), orc.spins)
 
 
+@pytest.mark.parametrize("rule,ratio,want", [(1, 0.5, [0] * 7 + [1] * 5), (0, 0.3, [0] * 6 + [1] * 6),
+                                              (0, 0.75, [0] * 9 + [1, 1, 0])],
+                         ids=["paper-rule", "ratio0.3", "ratio0.75"])
+def test_flatness_options_match_oracle(rule, ratio, want):
+    """The library's flatness test with the paper's rule (every reachable
+    entry within [avg/2, 2 avg], Sec. 3) and with other min/max thresholds:
+    every statistic and decision equals the oracle's on the same merged
+    histogram.  The expected decision sequences come from the oracle and
+    contain both outcomes."""
+    pm = _pm()
+    prob = Problem(ISING, 8, 64, 61)
+    with pm.Muca([prob], flat_rule=rule, flat_ratio=ratio) as ctx:
+        orc = _orc(prob)
+        got = []
+        for it in range(12):
+            print(f"  iteration {it}", flush=True)
+            st = ctx.iterate(1000)[0]
+            H, fl, _ = orc.iterate(1000, ratio=ratio, rule=rule)
+            assert np.array_equal(ctx.H(), H)
+            assert (bool(st["flat"]), bool(st["covered"])) == (fl.flat, fl.covered), f"iteration {it}"
+            assert (st["k_lo"], st["k_hi"], st["visited"], st["reachable"]) == (fl.k_lo, fl.k_hi, fl.visited,
+                                                                                 fl.reachable)
+            assert st["total"] == int(H.sum())
+            for key in ("min_over_max", "min_over_avg", "max_over_avg"):
+                assert st[key] == pytest.approx(getattr(fl, key), rel=1e-14, abs=0.0), key
+            got.append(int(fl.flat))
+        assert got == want
+
+
 def test_interface_tension_of_a_production_run():
     """8-state Potts L=16: weights iterated (with the correction function) to a
     flat histogram, a production run, then the equal-height analysis (Sec. 5,
