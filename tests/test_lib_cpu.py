@@ -80,3 +80,28 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
         pm.lib()
     with pytest.raises(pm.MucaError, match="missing"):
         _status([P(0, 8, 4)])
+
+
+def test_mlp_workspace_size_and_create_validation_without_gpu_calls():
+    """mucaMlpWorkspaceSize accepts 1..2^22 samples and grows with them;
+    mucaMlpCreate refuses a small, missing or misaligned workspace before
+    any GPU call."""
+    L = pm.lib()
+    sizes = {}
+    for n in (1, 1000, 1 << 22):
+        s = ctypes.c_size_t()
+        assert L.mucaMlpWorkspaceSize(n, ctypes.byref(s)) == 0
+        sizes[n] = s.value
+    assert sizes[1] < sizes[1000] < sizes[1 << 22]
+    # each sample holds 4 inputs and a target in float32 at least
+    assert sizes[1 << 22] - sizes[1] >= ((1 << 22) - 1) * 5 * 4
+    for bad in (0, -1, (1 << 22) + 1):
+        s = ctypes.c_size_t()
+        assert L.mucaMlpWorkspaceSize(bad, ctypes.byref(s)) != 0
+        assert "max_samples" in L.mucaMlpLastError(None).decode()
+    m = ctypes.c_void_p()
+    assert L.mucaMlpCreate(ctypes.byref(m), 1000, 1, ctypes.c_void_p(256), sizes[1000] - 1, None) != 0
+    assert not m.value and "workspace" in L.mucaMlpLastError(None).decode()
+    assert L.mucaMlpCreate(ctypes.byref(m), 1000, 1, None, sizes[1000], None) != 0
+    assert L.mucaMlpCreate(ctypes.byref(m), 1000, 1, ctypes.c_void_p(256 + 16), sizes[1000], None) != 0
+    assert "aligned" in L.mucaMlpLastError(None).decode()
