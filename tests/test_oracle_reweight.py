@@ -57,3 +57,35 @@ def test_production_run_reweights_to_exact_L4():
         assert ei == pytest.approx(ek, rel=0.01)
         assert ci == pytest.approx(ck, rel=0.05)
         assert mi == pytest.approx(aam / 16, rel=0.01)
+
+
+@pytest.mark.parametrize("q", [3, 4])
+def test_potts_reweighting_of_an_ideal_histogram_equals_derivatives_of_ln_z(q):
+    """q-state Potts on the 3x3 torus (E = -2N + k).  For any positive counts
+    c_k, the weights lnW = ln(c_k / Omega_k) make c the ideal histogram of the
+    ensemble Omega W, and Eq. (2) must return the exact canonical averages:
+    <E>/N = -d ln Z/d beta / N and C_V = beta^2 d^2 ln Z/d beta^2 / N, with
+    ln Z(beta) = ln sum_k Omega_k exp(-beta E_k) differentiated by mpmath.
+    Random counts catch a sign slip on lnW or on ln cnt; the energies catch
+    an Ising-style 2k."""
+    import mpmath
+    POTTS = oracle.POTTS
+    om, _ = oracle.bruteforce(POTTS, q, 3)
+    N = 9
+    mask = om > 0
+    rng = np.random.default_rng(q)
+    c = np.where(mask, rng.integers(1, 500, om.size), 0).astype(np.int64)
+    lnW = np.where(mask, np.log(np.maximum(c, 1)) - np.log(np.maximum(om, 1).astype(np.float64)), 0.0)
+    betas = [0.2, 0.9, 1.3, 2.0]
+    e, cv, _ = oracle.reweight(POTTS, 3, lnW, c, np.zeros_like(c), betas)
+    mpmath.mp.dps = 40
+    ks = [int(k) for k in np.nonzero(mask)[0]]
+
+    def lnz(b):
+        return mpmath.log(mpmath.fsum(int(om[k]) * mpmath.exp(-b * (-2 * N + k)) for k in ks))
+
+    for b, ei, ci in zip(betas, e, cv):
+        d1 = mpmath.diff(lnz, mpmath.mpf(b))
+        d2 = mpmath.diff(lnz, mpmath.mpf(b), 2)
+        assert ei == pytest.approx(float(-d1 / N), rel=1e-12)
+        assert ci == pytest.approx(float(b * b * d2 / N), rel=1e-10)
