@@ -148,6 +148,33 @@ def test_table_properties():
     assert np.all(T[:, 4] == 0xFFFFFFFF)
 
 
+def test_table_detailed_balance_for_energy_models():
+    """Metropolis on the multicanonical ensemble (Eq. 1): for every move k ->
+    k + dk and its reverse, one direction always accepts and the ratio of the
+    two acceptance probabilities is W(k + dk) / W(k) = e^(lnW[k+dk] - lnW[k]),
+    up to the quantisation of thresholds in units of 2^-32 (weight
+    differences up to 12 here, so the smaller threshold is at least 2^14)."""
+    rng = np.random.default_rng(17)
+    lnW = np.cumsum(rng.uniform(-3.0, 3.0, 257))
+    T = oracle.build_table(lnW).astype(np.float64)
+    n = lnW.size
+    checked = 0
+    for k in range(n):
+        for dk in range(1, 5):
+            t = k + dk
+            if t >= n:
+                continue
+            fwd, rev = T[k, dk + 4], T[t, -dk + 4]
+            assert max(fwd, rev) == 0xFFFFFFFF
+            # a threshold T accepts with probability T / 2^32; 0xFFFFFFFF always
+            pf = 1.0 if fwd == 0xFFFFFFFF else fwd / 2.0**32
+            pr = 1.0 if rev == 0xFFFFFFFF else rev / 2.0**32
+            d = lnW[t] - lnW[k]
+            assert pf / pr == pytest.approx(math.exp(d), rel=2.0 ** -13), (k, dk)
+            checked += 1
+    assert checked == 4 * n - 10
+
+
 def test_table_monotone_in_weight_difference():
     d = np.linspace(-30, 1, 4001)
     lnW = np.stack([np.zeros_like(d), d], axis=1)
