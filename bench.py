@@ -149,8 +149,8 @@ def main():
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by chains "
-              "with one histogram all-reduce per iteration, which this build does not run.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): runs over several GPUs, which would "
+              "shard by chains with one histogram all-reduce per iteration, are not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

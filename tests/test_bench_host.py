@@ -13,3 +13,13 @@ def test_code_text_ignores_comments_and_layout():
 def test_kernel_source_hash_is_stable():
     h = bench.kernel_source_hash()
     assert len(h) == 16 and h == bench.kernel_source_hash()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """Several GPUs are refused with a message, before any GPU is touched."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True,
+                         timeout=300)
+    assert res.returncode == 2
+    assert "one GPU only" in res.stderr and res.stdout == ""
