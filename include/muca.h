@@ -269,7 +269,9 @@ muca_status mucaSweepTiming(muca_ctx ctx, double *avg_ms, int32_t *n_launches);
  * per-chain histograms) into a caller-owned host buffer.  With blob == NULL
  * only *bytes is set.  mucaRestore loads such a blob into a context created
  * with the same problems; the continued run equals an uninterrupted one bit
- * for bit.  Both synchronise. */
+ * for bit.  Both synchronise.  Errors: MUCA_EINVAL for a buffer too small, a
+ * blob of another size or context, or a spin outside 0..q-1, all found before
+ * any state changes (k and M are recomputed from the spins, not read). */
 muca_status mucaCheckpoint(muca_ctx ctx, void *blob, size_t *bytes);
 muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes);
 

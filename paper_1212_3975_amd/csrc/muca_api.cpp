@@ -1215,7 +1215,16 @@ muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes) {
             (def.model == MUCA_ISING_MAG && def.beta != p.def.beta))
             return fail(ctx, MUCA_EINVAL, "checkpoint problem differs from the context");
         const size_t C = p.def.n_chains;
-        scan += sizeof(muca_problem) + (size_t)p.N * C + 8 * C + 8 * (size_t)p.nbins + 4 * (size_t)p.nbins * C;
+        // spins outside 0..q-1 would break the walkers' byte arithmetic and
+        // with it the tracked k that indexes the histograms
+        const uint8_t *sp = scan + sizeof(muca_problem);
+        const size_t ns = (size_t)p.N * C;
+        const uint8_t q = (uint8_t)p.def.q;
+        for (size_t i = 0; i < ns; ++i)
+            if (sp[i] >= q)
+                return fail(ctx, MUCA_EINVAL, "checkpoint spin %u out of range 0..%u in problem %zu", (unsigned)sp[i],
+                            (unsigned)(q - 1), (size_t)(&p - ctx->probs.data()));
+        scan += sizeof(muca_problem) + ns + 8 * C + 8 * (size_t)p.nbins + 4 * (size_t)p.nbins * C;
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {

@@ -443,3 +443,26 @@ def test_fast_walkers_long_launch_bit_exact(prob, n_sweeps, cw, rng_mode):
         assert np.array_equal(ctx.chain_hist(), orc.hist)
         assert np.array_equal(ctx.spins(), orc.spins)
         assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
+
+
+@pytest.mark.parametrize("prob,bad", [(Problem(ISING, 8, 16, 71), 2), (Problem(POTTS, 8, 16, 72, q=8), 8)],
+                         ids=["ising", "potts8"])
+def test_restore_rejects_out_of_range_spins(prob, bad):
+    """A checkpoint holding a spin outside 0..q-1 is refused on the host before
+    any state changes (no sweep runs on it); the intact blob still restores."""
+    import ctypes
+    pm = _pm()
+    with pm.Muca([prob]) as a:
+        a.iterate(100)
+        good = a.checkpoint()
+        blob = bytearray(good)
+        off = 32 + ctypes.sizeof(pm.Problem)          # header, then the problem, then the spins
+        assert max(blob[off:off + prob.L * prob.L * prob.n_chains]) < prob.q
+        blob[off + 5 * prob.n_chains + 3] = bad       # site 5 of chain 3
+        with pm.Muca([prob]) as b:
+            before = b.spins().copy()
+            with pytest.raises(pm.MucaError, match="out of range"):
+                b.restore(bytes(blob))
+            assert np.array_equal(b.spins(), before)
+            b.restore(good)
+            assert np.array_equal(b.spins(), a.spins()) and np.array_equal(b.k(), a.k())
