@@ -1,7 +1,9 @@
-"""The host code of libmuca under AddressSanitizer and UndefinedBehaviorSanitizer
-(no GPU): tests/native/host_sanitize.cpp drives every entry point that runs
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (no GPU).
+
+libmuca: tests/native/host_sanitize.cpp drives every entry point that runs
 without a device over ordinary, degenerate and invalid inputs.  The sanitizers
-instrument host code only; the kernels are compiled as usual and never run."""
+instrument host code only; the kernels are compiled as usual and never run.
+The oracle: its C code, built instrumented, runs every exported function."""
 import os
 import shutil
 import subprocess
@@ -29,3 +31,51 @@ def test_host_entry_points_are_clean_under_sanitizers(tmp_path):
     assert res.returncode == 0, res.stdout + res.stderr
     assert "Sanitizer" not in res.stderr and "runtime error" not in res.stderr, res.stderr
     assert "failures 0" in res.stdout
+
+
+_ORACLE_DRIVE = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+oracle._build.build = lambda force=False: sys.argv[2]
+assert oracle.lib()._name == sys.argv[2]
+oracle.philox((1, 2, 3, 4), (5, 6))
+oracle.reachable(oracle.ISING, 2, 6)
+oracle.reachable(oracle.POTTS, 8, 5)
+oracle.bruteforce(oracle.POTTS, 3, 3)
+oracle.bruteforce_canonical(oracle.ISING, 2, 4, 0.4)
+oracle.bruteforce_mag(4, 0.66)
+oracle.build_table_mag(6, 0.66, np.linspace(0.0, 3.0, 37))
+for model, L, q, beta in ((oracle.ISING, 6, 2, 0.0), (oracle.POTTS, 5, 8, 0.0), (oracle.POTTS, 3, 3, 0.0),
+                          (oracle.ISING_MAG, 6, 2, 0.66)):
+    r = oracle.OracleRun(model, L, 7, 11, q=q, n_threads=3, beta=beta)
+    for _ in range(3):
+        r.iterate(20, correct=(model != oracle.ISING_MAG))
+    r.production(5, 20)
+print("oracle drive ok")
+"""
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_is_clean_under_sanitizers(tmp_path):
+    """The oracle's C code (muca_oracle.c) built with AddressSanitizer and
+    UndefinedBehaviorSanitizer: every function it exports runs once, the
+    sampler on Ising, 8- and 3-state Potts and the multimagnetic ensemble
+    with several threads, with no report."""
+    so = str(tmp_path / "libmuca_oracle_san.so")
+    subprocess.run(["gcc", "-O1", "-g", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                    "-o", so, os.path.join(ROOT, "oracle", "muca_oracle.c"), "-lm", "-lpthread"],
+                   check=True, capture_output=True, timeout=300)
+    pre = [subprocess.run(["gcc", f"-print-file-name={n}"], capture_output=True, text=True).stdout.strip()
+           for n in ("libasan.so", "libubsan.so")]
+    if not all(os.path.isabs(p) and os.path.exists(p) for p in pre):
+        pytest.skip("sanitizer runtimes not found")
+    env = dict(os.environ, LD_PRELOAD=":".join(pre), ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="print_stacktrace=1")
+    import sys
+    res = subprocess.run([sys.executable, "-c", _ORACLE_DRIVE, ROOT, so], capture_output=True, text=True,
+                         timeout=600, env=env)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "runtime error" not in res.stderr and "Sanitizer" not in res.stderr, res.stderr
+    assert "oracle drive ok" in res.stdout
