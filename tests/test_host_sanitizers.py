@@ -3,7 +3,8 @@
 libmuca: tests/native/host_sanitize.cpp drives every entry point that runs
 without a device over ordinary, degenerate and invalid inputs.  The sanitizers
 instrument host code only; the kernels are compiled as usual and never run.
-The oracle: its C code, built instrumented, runs every exported function."""
+The oracle: its C code, built instrumented, runs every exported function, and
+its threaded sweeps run under ThreadSanitizer."""
 import os
 import shutil
 import subprocess
@@ -79,3 +80,38 @@ def test_oracle_is_clean_under_sanitizers(tmp_path):
     assert res.returncode == 0, res.stdout + res.stderr
     assert "runtime error" not in res.stderr and "Sanitizer" not in res.stderr, res.stderr
     assert "oracle drive ok" in res.stdout
+
+
+_ORACLE_THREADS = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import oracle
+oracle._build.build = lambda force=False: sys.argv[2]
+assert oracle.lib()._name == sys.argv[2]
+for model, L, q, beta in ((oracle.ISING, 6, 2, 0.0), (oracle.POTTS, 5, 8, 0.0), (oracle.ISING_MAG, 6, 2, 0.66)):
+    r = oracle.OracleRun(model, L, 13, 11, q=q, n_threads=4, beta=beta)
+    for _ in range(3):
+        r.iterate(20)
+    r.production(5, 20)
+print("oracle threads ok")
+"""
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_threads_are_clean_under_thread_sanitizer(tmp_path):
+    """The oracle's sweeps split the chains over threads; built with
+    ThreadSanitizer, four threads over 13 chains report no data race."""
+    so = str(tmp_path / "libmuca_oracle_tsan.so")
+    subprocess.run(["gcc", "-O1", "-g", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-fsanitize=thread", "-o", so, os.path.join(ROOT, "oracle", "muca_oracle.c"), "-lm", "-lpthread"],
+                   check=True, capture_output=True, timeout=300)
+    rt = subprocess.run(["gcc", "-print-file-name=libtsan.so"], capture_output=True, text=True).stdout.strip()
+    if not (os.path.isabs(rt) and os.path.exists(rt)):
+        pytest.skip("thread sanitizer runtime not found")
+    env = dict(os.environ, LD_PRELOAD=rt, TSAN_OPTIONS="halt_on_error=1")
+    import sys
+    res = subprocess.run([sys.executable, "-c", _ORACLE_THREADS, ROOT, so], capture_output=True, text=True,
+                         timeout=600, env=env)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "ThreadSanitizer" not in res.stderr, res.stderr
+    assert "oracle threads ok" in res.stdout
