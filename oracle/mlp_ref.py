@@ -5,8 +5,11 @@ Plain numpy in float64: 4 -> 64 -> 64 -> 64 -> 1 with the tanh form of GELU
 rounding on, every matrix-product input (inputs, weights, biases,
 activations and back-propagated pre-activation gradients) is rounded to
 bfloat16 (round to nearest even, through float32) at the same points as the
-HIP kernels; with rounding off the function is the exact float64 network,
-whose gradient a finite-difference check pins.
+HIP kernels; with rounding off the function is the exact float64 network.
+Pins: the float64 gradient against central finite differences, the rounding
+against hand-worked bfloat16 cases, GELU against the exact x*Phi(x) within the
+tanh form's error, and Adam (Kingma and Ba) against the closed forms of its
+first step, of a constant gradient and of a single impulse.
 
 Parameter vector layout (8705 floats): W1[64][4], b1[64], W2[64][64], b2[64],
 W3[64][64], b3[64], W4[64], b4[1].
