@@ -8,6 +8,8 @@ The sampler, table and recursion are plain C loops (``muca_oracle.c``); this
 module wraps them with ctypes and adds, in plain numpy:
   - the flatness test of the weight iteration (Sec. 3: full range covered and
     every entry within bounds of the others);
+  - the correction function (Sec. 3), which continues lnW linearly beyond the
+    sampled region after a recursion;
   - time-series reweighting, Eq. (2), written over energy bins;
   - the interface tension of Eq. (9) from the equal-height reweighted
     energy histogram (Sec. 5).
