@@ -119,7 +119,8 @@ def test(params_path: str, out_dir: str, sizes, chains: int, sweeps: int, cap_pl
                        "sweeps_per_iter": sweeps, "flat": n_flat is not None, "iterations": iters,
                        "sweeps_per_chain": iters * sweeps, "total_sweeps": iters * sweeps * chains,
                        "seconds": round(time.time() - t0, 2),
-                       "last_visited": hist[-1]["visited"], "reachable": hist[-1]["reachable"]}
+                       "last_visited": hist[-1]["visited"] if hist else None,
+                       "reachable": hist[-1]["reachable"] if hist else None}
                 results.append(rec)
                 print(json.dumps(rec), flush=True)
                 with open(os.path.join(out_dir, "test_results.json"), "w") as fh:

@@ -1,6 +1,7 @@
-"""Host-side helpers of the interface-tension driver (Sec. 5): the 1/L fit,
-the per-site carry-over of converged weights between lattice sizes, and the
-8-state Potts transition point.  No GPU."""
+"""Host-side helpers of the drivers, no GPU: of the interface-tension driver
+(Sec. 5) the 1/L fit, the per-site carry-over of converged weights between
+lattice sizes and the 8-state Potts transition point; of the learned-weights
+driver the loop that iterates to a flat histogram."""
 import math
 
 import numpy as np
@@ -67,3 +68,34 @@ def test_rescaled_weights_keep_the_per_site_values_at_shared_energies():
     np.testing.assert_allclose(out[::4] / N, lnW / Np, rtol=1e-12, atol=1e-12)
     mid = out[2::4][: 2 * Np] / N
     np.testing.assert_allclose(mid, 0.5 * (lnW[:-1] + lnW[1:]) / Np, rtol=1e-12, atol=1e-12)
+
+
+class _ScriptedContext:
+    """Stands in for a library context: iterate() returns scripted flatness."""
+
+    def __init__(self, flats):
+        self.flats = list(flats)
+        self.calls = []
+
+    def iterate(self, sweeps):
+        self.calls.append(sweeps)
+        flat = self.flats[len(self.calls) - 1]
+        return [{"visited": 10, "reachable": 12, "min_over_max": 0.6 if flat else 0.1, "flat": flat}]
+
+
+def test_iterate_to_flat_stops_at_the_first_flat_iteration():
+    from paper_1212_3975_amd.learned_init import iterate_to_flat
+    ctx = _ScriptedContext([False, False, True, True])
+    n, hist = iterate_to_flat(ctx, 500, cap=10, label="t")
+    assert n == 3 and len(hist) == 3 and ctx.calls == [500, 500, 500]
+    assert [h["it"] for h in hist] == [1, 2, 3] and hist[-1]["flat"]
+
+
+def test_iterate_to_flat_respects_the_cap_and_the_time_limit():
+    from paper_1212_3975_amd.learned_init import iterate_to_flat
+    ctx = _ScriptedContext([False] * 20)
+    n, hist = iterate_to_flat(ctx, 100, cap=7, label="t")
+    assert n is None and len(hist) == 7 and len(ctx.calls) == 7
+    ctx = _ScriptedContext([False] * 20)
+    n, hist = iterate_to_flat(ctx, 100, cap=7, label="t", max_seconds=-1.0)
+    assert n is None and hist == [] and ctx.calls == []
