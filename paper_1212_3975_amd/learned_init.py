@@ -59,6 +59,8 @@ def iterate_to_flat(ctx, sweeps: int, cap: int, label: str, log_every: int = 10,
 
 def train(out_dir: str, chains: int, sweeps_ising: int, sweeps_potts: int, cap: int, refine: int, steps: int,
           max_seconds: float):
+    if steps < 3:
+        raise ValueError("steps must be at least 3 (three learning-rate stages)")
     os.makedirs(out_dir, exist_ok=True)
     mlp = pm.Mlp(max_samples=1 << 15, seed=1)
     runs = []

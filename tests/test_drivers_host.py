@@ -99,3 +99,9 @@ def test_iterate_to_flat_respects_the_cap_and_the_time_limit():
     ctx = _ScriptedContext([False] * 20)
     n, hist = iterate_to_flat(ctx, 100, cap=7, label="t", max_seconds=-1.0)
     assert n is None and hist == [] and ctx.calls == []
+
+
+def test_training_needs_three_steps():
+    from paper_1212_3975_amd.learned_init import train
+    with pytest.raises(ValueError, match="at least 3"):
+        train("/nonexistent", chains=4, sweeps_ising=1, sweeps_potts=1, cap=1, refine=0, steps=2, max_seconds=1.0)
