@@ -157,6 +157,9 @@ def main():
     import paper_1212_3975_amd as pm
     from workloads import C2, C3, C4, C_MAG, ISING, Problem
 
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU: none is visible to this process.", file=sys.stderr)
+        sys.exit(2)
     if args.scan_chains:
         from workloads import POTTS
         scan_chains(args.scan_chains, pm, torch, Problem, POTTS if args.scan_model == "potts8" else ISING)

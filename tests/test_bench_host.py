@@ -23,3 +23,18 @@ def test_bench_refuses_more_than_one_gpu():
                          timeout=300)
     assert res.returncode == 2
     assert "one GPU only" in res.stderr and res.stdout == ""
+
+
+def test_bench_without_a_gpu_exits_with_a_message():
+    """Without a visible GPU the benchmark stops with a message; it never falls
+    back to another path."""
+    import subprocess
+    import sys
+
+    import pytest
+    from conftest import gpu_available
+    if gpu_available():
+        pytest.skip("a GPU is visible")
+    res = subprocess.run([sys.executable, bench.__file__, "--no-cpu"], capture_output=True, text=True, timeout=300)
+    assert res.returncode == 2
+    assert "needs an MI355X GPU" in res.stderr and res.stdout == ""
