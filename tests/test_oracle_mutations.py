@@ -1,0 +1,90 @@
+"""Planted mistakes in the oracle, on the CPU.  Each mutation below is applied
+to a copy of oracle/ in a temporary folder (the repository's files are never
+touched); the copy's C library is built there and the pin tests that should
+notice the mistake run against it in a subprocess, where they must fail.  The
+unmutated copy passes the same selections.  This shows that the pins
+constrain the oracle where a plausible slip would change it."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, file under oracle/, text, replacement, pin file, -k selection)
+MUTATIONS = [
+    ("dk-sign", "muca_oracle.c", "int dk = after - before;", "int dk = before - after;",
+     "test_oracle_pins.py", "tracked_state"),
+    ("table-direction", "muca_oracle.c", "v = threshold_of(lnW[t] - lnW[k]);", "v = threshold_of(lnW[k] - lnW[t]);",
+     "test_oracle_pins.py", "table_"),
+    ("potts-proposal-range", "muca_oracle.c", "(uint64_t)(j->q - 1)) >> 32);", "(uint64_t)(j->q)) >> 32);",
+     "test_oracle_pins.py", "infinite_temperature"),
+    ("up-neighbour", "muca_oracle.c", "nb[3] = ((y + L - 1) % L) * L + x; /* up    */",
+     "nb[3] = ((y + L - 1) % L) * L + (x + 1) % L; /* up    */", "test_oracle_pins.py", "tracked_state"),
+    ("abs-m", "muca_oracle.c",
+     "if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + k] += (m < 0) ? -m : m;",
+     "if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + k] += m;",
+     "test_oracle_reweight.py", "production_run"),
+    ("mag-beta-sign", "muca_oracle.c", "- beta * (double)(2 * dk))", "+ beta * (double)(2 * dk))",
+     "test_oracle_mag.py", "canonical_magnetization"),
+    ("mag-spin-columns", "muca_oracle.c", "(s[i] ? 5 : 0)]", "(s[i] ? 0 : 5)]",
+     "test_oracle_mag.py", "canonical_magnetization"),
+    ("mag-m-direction", "muca_oracle.c", "int t = u ? m - 1 : m + 1;", "int t = u ? m + 1 : m - 1;",
+     "test_oracle_mag.py", "canonical_magnetization or detailed_balance"),
+    ("reweight-lnw-sign", "__init__.py", "a = np.log(ck) - lw - beta * Ek", "a = np.log(ck) + lw - beta * Ek",
+     "test_oracle_reweight.py", "kaufman or potts"),
+    ("potts-energy", "__init__.py", "return -2.0 * N + (2.0 * k if model == ISING else k)", "return -2.0 * N + 2.0 * k",
+     "test_oracle_reweight.py", "potts"),
+    ("flatness-strict", "__init__.py", "flat = covered and mom >= ratio", "flat = covered and mom > ratio",
+     "test_oracle_pins.py", "flatness"),
+    ("eqh-beta-sign", "__init__.py", "- beta * E[ks]", "+ beta * E[ks]",
+     "test_oracle_interface.py", "closed_form"),
+    ("eqh-bisection", "__init__.py", "if gap(mid) < 0.0:", "if gap(mid) > 0.0:",
+     "test_oracle_interface.py", "closed_form"),
+    ("eqh-plain-valley", "__init__.py",
+     "score = np.minimum(left, right) - a - np.abs(np.log(m_left) - np.log(m_right))",
+     "score = np.minimum(left, right) - a", "test_oracle_interface.py", "sparse_tail"),
+    ("gelu-coefficient", "mlp_ref.py", "t = np.tanh(_C * (z + 0.044715 * z ** 3))", "t = np.tanh(_C * (z + 0.04 * z ** 3))",
+     "test_oracle_mlp.py", "gelu"),
+    ("adam-no-correction", "mlp_ref.py", "mh = m / (1 - b1 ** step)", "mh = m", "test_oracle_mlp.py", "adam"),
+]
+
+
+def _copy(tmp, pin_file):
+    shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(tmp, "oracle"),
+                    ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
+    os.makedirs(os.path.join(tmp, "tests"))
+    for f in ("conftest.py", "exact_ising.py", pin_file):
+        shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(tmp, "tests", f))
+    shutil.copytree(os.path.join(ROOT, "tests", "golden"), os.path.join(tmp, "tests", "golden"))
+
+
+def _run(tmp, pin_file, selection):
+    return subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-k", selection,
+                           os.path.join(tmp, "tests", pin_file)], cwd=tmp, capture_output=True, text=True,
+                          timeout=600)
+
+
+@pytest.mark.parametrize("name,fname,old,new,pin_file,selection", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_fails_a_pin(tmp_path, name, fname, old, new, pin_file, selection):
+    tmp = str(tmp_path)
+    _copy(tmp, pin_file)
+    path = os.path.join(tmp, "oracle", fname)
+    src = open(path).read()
+    assert src.count(old) == 1, f"{name}: the text to mutate must occur exactly once"
+    with open(path, "w") as fh:
+        fh.write(src.replace(old, new))
+    res = _run(tmp, pin_file, selection)
+    # exit status 1: tests ran and at least one failed (2-5 would be errors or nothing collected)
+    assert res.returncode == 1 and " failed" in res.stdout, res.stdout[-3000:] + res.stderr[-2000:]
+
+
+@pytest.mark.parametrize("pin_file", sorted({m[4] for m in MUTATIONS}))
+def test_unmutated_copy_passes_the_same_selections(tmp_path, pin_file):
+    tmp = str(tmp_path)
+    _copy(tmp, pin_file)
+    selection = " or ".join(sorted({f"({m[5]})" for m in MUTATIONS if m[4] == pin_file}))
+    res = _run(tmp, pin_file, selection)
+    assert res.returncode == 0 and " passed" in res.stdout, res.stdout[-3000:] + res.stderr[-2000:]
