@@ -31,6 +31,11 @@ MUTATIONS = [
      "test_oracle_mag.py", "canonical_magnetization"),
     ("mag-spin-columns", "muca_oracle.c", "(s[i] ? 5 : 0)]", "(s[i] ? 0 : 5)]",
      "test_oracle_mag.py", "canonical_magnetization"),
+    ("mag-factor-2", "muca_oracle.c", "- beta * (double)(2 * dk))", "- beta * (double)(dk))",
+     "test_oracle_mag.py", "canonical_magnetization"),
+    ("mag-k-sum", "muca_oracle.c", "if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + b] += k;",
+     "if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + b] += k + 1;",
+     "test_oracle_mag.py", "canonical_magnetization"),
     ("mag-m-direction", "muca_oracle.c", "int t = u ? m - 1 : m + 1;", "int t = u ? m + 1 : m - 1;",
      "test_oracle_mag.py", "canonical_magnetization or detailed_balance"),
     ("reweight-lnw-sign", "__init__.py", "a = np.log(ck) - lw - beta * Ek", "a = np.log(ck) + lw - beta * Ek",
@@ -43,12 +48,18 @@ MUTATIONS = [
      "test_oracle_interface.py", "closed_form"),
     ("eqh-bisection", "__init__.py", "if gap(mid) < 0.0:", "if gap(mid) > 0.0:",
      "test_oracle_interface.py", "closed_form"),
+    ("eqh-one-over-l", "__init__.py", "/ (2.0 * L), ks", "/ (1.0 * L), ks",
+     "test_oracle_interface.py", "closed_form"),
+    ("eqh-drop-ln-cnt", "__init__.py", "a = np.log(np.asarray(cnt, np.float64)[ks]) - ",
+     "a = 0.0 * np.log(np.asarray(cnt, np.float64)[ks]) - ", "test_oracle_interface.py", "uses_the_counts"),
     ("eqh-plain-valley", "__init__.py",
      "score = np.minimum(left, right) - a - np.abs(np.log(m_left) - np.log(m_right))",
      "score = np.minimum(left, right) - a", "test_oracle_interface.py", "sparse_tail"),
     ("gelu-coefficient", "mlp_ref.py", "t = np.tanh(_C * (z + 0.044715 * z ** 3))", "t = np.tanh(_C * (z + 0.04 * z ** 3))",
      "test_oracle_mlp.py", "gelu"),
     ("adam-no-correction", "mlp_ref.py", "mh = m / (1 - b1 ** step)", "mh = m", "test_oracle_mlp.py", "adam"),
+    ("adam-rates-swapped", "mlp_ref.py", "def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):",
+     "def adam(p, g, m, v, step, lr, b1=0.999, b2=0.9, eps=1e-8):", "test_oracle_mlp.py", "adam"),
 ]
 
 
