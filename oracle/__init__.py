@@ -355,8 +355,8 @@ def _valley_split(model, L, lnW, cnt, beta_lo, beta_hi):
     histogram, taken where the histogram is most clearly double-peaked: over 65
     equally spaced beta in the bracket, the best-scoring valley (its depth less
     the log ratio of the probabilities on its two sides) at the beta where
-    that score is highest.  A split fixed in k makes the peak-height difference below a
-    continuous, increasing function of beta."""
+    that score is highest.  A split fixed in k makes the peak-height
+    difference below a continuous, increasing function of beta."""
     best, split = 0.0, None
     for i in range(65):
         b = beta_lo + (beta_hi - beta_lo) * i / 64.0
@@ -386,11 +386,12 @@ def interface_tension(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: flo
     """Order-disorder interface tension, Eq. (9), Sec. 5.
 
     Step 1: find the inverse temperature at which the histogram reweighted to
-    the canonical ensemble has its two peaks at the same height (bisection on the
-    difference of the two log peak heights on either side of the valley bin,
-    which grows with beta because the ordered side has the lower energies).  Step 2: sigma_od = ln(P_max/P_min) /
-    (2L) there, with P_max the common peak height.  Returns (beta, sigma,
-    (k_ordered, k_min, k_disordered))."""
+    the canonical ensemble has its two peaks at the same height (bisection on
+    the difference of the two log peak heights on either side of the valley
+    bin, which grows with beta because the ordered side has the lower
+    energies).  Step 2: sigma_od = ln(P_max/P_min) / (2L) there, with P_max
+    the common peak height.  Returns (beta, sigma, (k_ordered, k_min,
+    k_disordered))."""
     lo, hi = float(beta_lo), float(beta_hi)
     split = _valley_split(model, L, lnW, cnt, lo, hi)
 
