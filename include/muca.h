@@ -6,7 +6,7 @@
  *   - Sec. 2, Eq. (1): sample with weights W(E) instead of exp(-beta E); with
  *     W = 1/Omega the energy histogram is flat;
  *   - Sec. 2: the weights are found iteratively, W <- W / H, kept in logs;
- *   - Sec. 2, "Parallel Version": p independent chains share W, each fills its
+ *   - Sec. 2, the parallel version: p independent chains share W, each fills its
  *     own histogram H_i, the histograms are summed, the new W is sent back;
  *   - Sec. 3, Eqs. (3)-(4): 2D Ising and q-state Potts models on an L x L
  *     periodic square lattice, sweeps of V = L^2 single-spin updates, a start
