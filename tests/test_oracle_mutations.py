@@ -36,6 +36,8 @@ MUTATIONS = [
     ("mag-k-sum", "muca_oracle.c", "if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + b] += k;",
      "if (j->record == REC_PROD) j->sabs[(size_t)c * j->n_bins + b] += k + 1;",
      "test_oracle_mag.py", "canonical_magnetization"),
+    ("mag-dk-column", "muca_oracle.c", "(dk + 4) / 2 + (s[i]", "(4 - dk) / 2 + (s[i]",
+     "test_oracle_mag.py", "canonical_magnetization"),
     ("mag-m-direction", "muca_oracle.c", "int t = u ? m - 1 : m + 1;", "int t = u ? m + 1 : m - 1;",
      "test_oracle_mag.py", "canonical_magnetization or detailed_balance"),
     ("reweight-lnw-sign", "__init__.py", "a = np.log(ck) - lw - beta * Ek", "a = np.log(ck) + lw - beta * Ek",
@@ -57,6 +59,10 @@ MUTATIONS = [
      "score = np.minimum(left, right) - a", "test_oracle_interface.py", "sparse_tail"),
     ("gelu-coefficient", "mlp_ref.py", "t = np.tanh(_C * (z + 0.044715 * z ** 3))", "t = np.tanh(_C * (z + 0.04 * z ** 3))",
      "test_oracle_mlp.py", "gelu"),
+    ("gelu-derivative", "mlp_ref.py", "(1.0 + 3 * 0.044715 * z * z)", "(1.0 + 2 * 0.044715 * z * z)",
+     "test_oracle_mlp.py", "gelu or finite_differences"),
+    ("adam-correction-off-by-one", "mlp_ref.py", "vh = v / (1 - b2 ** step)", "vh = v / (1 - b2 ** (step + 1))",
+     "test_oracle_mlp.py", "adam"),
     ("adam-no-correction", "mlp_ref.py", "mh = m / (1 - b1 ** step)", "mh = m", "test_oracle_mlp.py", "adam"),
     ("adam-rates-swapped", "mlp_ref.py", "def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):",
      "def adam(p, g, m, v, step, lr, b1=0.999, b2=0.9, eps=1e-8):", "test_oracle_mlp.py", "adam"),
