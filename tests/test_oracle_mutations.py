@@ -57,6 +57,13 @@ MUTATIONS = [
     ("eqh-plain-valley", "__init__.py",
      "score = np.minimum(left, right) - a - np.abs(np.log(m_left) - np.log(m_right))",
      "score = np.minimum(left, right) - a", "test_oracle_interface.py", "sparse_tail"),
+    ("eqh-height-balance", "__init__.py",
+     "score = np.minimum(left, right) - a - np.abs(np.log(m_left) - np.log(m_right))",
+     "score = np.minimum(left, right) - a - np.abs(left - right)", "test_oracle_interface.py",
+     "ground_state or sparse_tail"),
+    ("eqh-split-moves-with-beta", "__init__.py", "low, high = ks <= split, ks > split",
+     "mean = int(np.average(ks, weights=np.exp(a - a.max()))); low, high = ks <= mean, ks > mean",
+     "test_oracle_interface.py", "wide_bracket"),
     ("gelu-coefficient", "mlp_ref.py", "t = np.tanh(_C * (z + 0.044715 * z ** 3))", "t = np.tanh(_C * (z + 0.04 * z ** 3))",
      "test_oracle_mlp.py", "gelu"),
     ("gelu-derivative", "mlp_ref.py", "(1.0 + 3 * 0.044715 * z * z)", "(1.0 + 2 * 0.044715 * z * z)",
