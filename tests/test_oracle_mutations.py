@@ -15,6 +15,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # (name, file under oracle/, text, replacement, pin file, -k selection)
 MUTATIONS = [
+    ("philox-multiplier", "muca_oracle.c", "0xD2511F53u", "0xD2511F55u", "test_oracle_pins.py", "known_answers"),
+    ("philox-key-schedule", "muca_oracle.c", "k[1] += 0xBB67AE85u;", "k[1] += 0xBB67AE86u;",
+     "test_oracle_pins.py", "known_answers"),
+    ("bond-count", "muca_oracle.c", "if (s[i] != s[nb[2]]) ++k;", "if (s[i] != s[nb[0]]) ++k;",
+     "test_oracle_pins.py", "kaufman_beale"),
+    ("ising-reachable", "muca_oracle.c", "r = (k % 2 == 0) && k != 2 && k != 2 * N - 2;",
+     "r = (k % 2 == 0) && k != 2;", "test_oracle_pins.py", "beale_invariants"),
+    ("recursion-sign", "muca_oracle.c", "if (H[b] > 0) lnW[b] -= log((double)H[b]);",
+     "if (H[b] > 0) lnW[b] += log((double)H[b]);", "test_oracle_pins.py", "converges_to_exact_dos_ising_L4"),
+    ("correction-slope", "__init__.py", "slope = (lnW[lo] - lnW[a]) / float(lo - a)",
+     "slope = (lnW[lo] - lnW[a]) / float(a - lo)", "test_oracle_pins.py", "correction"),
     ("dk-sign", "muca_oracle.c", "int dk = after - before;", "int dk = before - after;",
      "test_oracle_pins.py", "tracked_state"),
     ("table-direction", "muca_oracle.c", "v = threshold_of(lnW[t] - lnW[k]);", "v = threshold_of(lnW[k] - lnW[t]);",
