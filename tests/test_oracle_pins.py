@@ -115,6 +115,31 @@ def test_bruteforce_potts_L3_closed_forms(potts_l3):
     assert np.array_equal(om > 0, oracle.reachable(POTTS, 8, 3))
 
 
+def _potts_transfer_matrix_z(q, L, x):
+    """sum_k Omega(k) x^k on the L x L torus by a transfer matrix over row
+    states (an independent route to the partition function): M[a][b] =
+    x^(unsatisfied bonds inside row a + between row a and the row b below),
+    and the sum over configurations is Tr(M^L)."""
+    import itertools
+    rows = np.array(list(itertools.product(range(q), repeat=L)))
+    inside = (rows != np.roll(rows, -1, axis=1)).sum(axis=1)
+    between = (rows[:, None, :] != rows[None, :, :]).sum(axis=2)
+    M = float(x) ** (inside[:, None] + between).astype(np.float64)
+    return float(np.trace(np.linalg.matrix_power(M, L)))
+
+
+@pytest.mark.parametrize("q,L", [(8, 3), (3, 4)])
+def test_bruteforce_potts_equals_transfer_matrix(q, L, potts_l3):
+    """Every bin of the enumerated Potts Omega(k): the polynomial
+    sum_k Omega(k) x^k has degree 2N, so agreeing with the transfer matrix at
+    2N + 1 distinct x fixes all of its coefficients."""
+    om = potts_l3[0] if (q, L) == (8, 3) else oracle.bruteforce(POTTS, q, L)[0]
+    N = L * L
+    for x in np.linspace(0.05, 1.0, 2 * N + 1):
+        direct = float(np.polynomial.polynomial.polyval(x, om.astype(np.float64)))
+        assert direct == pytest.approx(_potts_transfer_matrix_z(q, L, x), rel=1e-11), (q, L, x)
+
+
 def test_ising_equals_two_state_potts():
     """The Ising model is the q = 2 Potts model (Sec. 3): both count k the
     same way, so brute-force Omega(k) agrees."""
