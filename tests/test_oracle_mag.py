@@ -97,3 +97,54 @@ def test_iterated_weights_converge_to_minus_log_p():
     assert np.ptp(c) < 0.25, c
     # the two ordered peaks are far more likely than M = 0 at 1.5 beta_0
     assert p_exact[0] / p_exact[N // 2] > 10.0
+
+
+def _ising_omega_k_m(L):
+    """Omega(k, m) of the L x L Ising torus (k unsatisfied bonds, m up spins)
+    by a transfer matrix over row states: the rows of a configuration form a
+    cycle a_0 .. a_{L-1}, each row contributes its own unsatisfied bonds, the
+    bonds to the row below and its up spins.  Polynomials in (x^k, y^m) are
+    carried as count arrays.  Independent of the oracle's enumeration."""
+    import itertools
+    N = L * L
+    rows = np.array(list(itertools.product((0, 1), repeat=L)))
+    inside = (rows != np.roll(rows, -1, axis=1)).sum(axis=1)
+    between = (rows[:, None, :] != rows[None, :, :]).sum(axis=2)
+    ups = rows.sum(axis=1)
+    S = rows.shape[0]
+    total = np.zeros((2 * N + 1, N + 1))
+    for a0 in range(S):
+        vec = np.zeros((S, 2 * N + 1, N + 1))
+        vec[a0, 0, 0] = 1.0
+        for step in range(L):
+            new = np.zeros_like(vec)
+            for a in range(S):
+                if not vec[a].any():
+                    continue
+                for b in range(S):
+                    if step == L - 1 and b != a0:
+                        continue
+                    dk, dm = inside[a] + between[a, b], ups[a]
+                    new[b, dk:, dm:] += vec[a, :2 * N + 1 - dk, :N + 1 - dm]
+            vec = new
+        total += vec[a0]
+    return total
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.66])
+def test_bruteforce_mag_equals_transfer_matrix(beta):
+    """The enumerated canonical P(m) and mean k per m of L = 4 equal those of
+    the transfer matrix; summed over m, its Omega(k) is Beale's."""
+    import exact_ising
+    L = 4
+    om = _ising_omega_k_m(L)
+    assert om.sum() == 2 ** 16
+    assert list(om.sum(axis=1).astype(np.int64)) == [int(v) for v in exact_ising.density_of_states(L)]
+    k = np.arange(om.shape[0])[:, None]
+    w = om * np.exp(-2.0 * beta * k)             # e^{-beta E} with E = -2N + 2k, up to a constant
+    p_tm = w.sum(axis=0) / w.sum()
+    km_tm = (w * k).sum(axis=0) / w.sum(axis=0)
+    p, km = oracle.bruteforce_mag(L, beta)
+    # the enumeration sums 2^16 weights in another order: agreement to rounding
+    np.testing.assert_allclose(p, p_tm, rtol=1e-10)
+    np.testing.assert_allclose(km, km_tm, rtol=1e-10)

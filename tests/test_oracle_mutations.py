@@ -49,6 +49,8 @@ MUTATIONS = [
      "test_oracle_mag.py", "canonical_magnetization"),
     ("mag-dk-column", "muca_oracle.c", "(dk + 4) / 2 + (s[i]", "(4 - dk) / 2 + (s[i]",
      "test_oracle_mag.py", "canonical_magnetization"),
+    ("mag-enumeration-energy", "muca_oracle.c", "double w = exp(-beta * ((-2.0 * N + 2.0 * k) - e_ground));",
+     "double w = exp(-beta * ((-2.0 * N + 1.0 * k) - e_ground));", "test_oracle_mag.py", "transfer_matrix"),
     ("mag-m-direction", "muca_oracle.c", "int t = u ? m - 1 : m + 1;", "int t = u ? m + 1 : m - 1;",
      "test_oracle_mag.py", "canonical_magnetization or detailed_balance"),
     ("reweight-lnw-sign", "__init__.py", "a = np.log(ck) - lw - beta * Ek", "a = np.log(ck) + lw - beta * Ek",
