@@ -5,11 +5,14 @@ sweeps (the sweep kernel), the per-chain histograms are merged, the
 recursion lnW <- lnW - ln H is applied and the acceptance tables are
 rebuilt.  The default workload is 2D Ising L = 64 with 4096 chains and 2000
 sweeps per iteration; --workload potts32 (8-state Potts L = 32, 4096 chains,
-5000 sweeps) and --workload mixed (nine problems of 512 chains in one launch,
-2000 sweeps) measure the other configurations.  Inputs (spins, tables) are
+5000 sweeps), --workload mixed (nine problems of 512 chains in one launch,
+2000 sweeps), mag32 (multimagnetic Ising L = 32) and ising96, ising128,
+potts48 (8192 chains, the learned-initial-weights test sizes) measure the
+other configurations.  Inputs (spins, tables) are
 resident in HBM before the timed region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload ising64|potts32|mixed]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                  [--workload ising64|potts32|mixed|mag32|ising96|ising128|potts48]
 """
 import argparse
 import hashlib
@@ -32,6 +35,19 @@ METRIC = "spin-update attempts/s (G/s) + %roofline; sweeps-to-flat, learned vs p
 OPS_PER_ISING_UPDATE = 32
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one int32 op per lane per cycle.
 PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9
+CLOCK_HZ = 2.4e9
+OPS_DERIVATION = {
+    "ising": "Philox4x32-10: 10 rounds x (2 mul_lo + 2 mul_hi + 4 xor) = 80 lane ops per block of four words, "
+             "20 per update; the update: 4 neighbour compares, 3 adds, 2 table-index ops, 1 compare, 2 state ops "
+             "= 12; 32 in all.  An estimate that also counts the lane selects of the update (16 ops) gives 36 and "
+             "a fraction 1.125 times this one",
+    "potts": "half a Philox block (40) + 8 neighbour compares, 6 adds, proposal 3, table index 2, compare 1, "
+             "state 2 = 62",
+}
+# Each update of a chain reads the table entry its previous update selected:
+# at least one LDS read latency per site and chain (about 68 cycles measured
+# with every CU busy), whatever the instruction count.
+LDS_LATENCY_CYCLES = 68
 
 
 def code_text(src: str) -> str:
@@ -77,21 +93,43 @@ def host_cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(prob, sweeps: int, n_chains: int):
+def host_cores():
+    """(cores this process may run on, cores the machine reports)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return usable, os.cpu_count() or 1
+
+
+def cpu_baseline(prob, sweeps: int, n_chains: int, single_chains: int):
     """The oracle as it stands, on the host cores, on a bounded sample of the
-    same workload: n_chains chains for `sweeps` sweeps."""
+    same workload: n_chains chains for `sweeps` sweeps on every thread the
+    oracle uses, then single_chains chains on one thread."""
     import oracle
+
+    def run(chains, threads):
+        orc = oracle.OracleRun(prob.model, prob.L, chains, prob.seed, q=prob.q, n_threads=threads,
+                               beta=getattr(prob, "beta", 0.0))
+        t0 = time.perf_counter()
+        orc.sweeps(sweeps, oracle.REC_MUCA)
+        dt = time.perf_counter() - t0
+        return chains * sweeps * prob.N / dt, dt
+
     threads = oracle.default_threads()
-    orc = oracle.OracleRun(prob.model, prob.L, n_chains, prob.seed, q=prob.q, n_threads=threads,
-                           beta=getattr(prob, "beta", 0.0))
-    t0 = time.perf_counter()
-    orc.sweeps(sweeps, oracle.REC_MUCA)
-    dt = time.perf_counter() - t0
-    ups = n_chains * sweeps * prob.N / dt
+    usable, reported = host_cores()
+    ups, dt = run(n_chains, threads)
+    ups1, dt1 = run(single_chains, 1)
+    name = ["Ising", str(prob.q) + "-state Potts", "multimagnetic Ising"][prob.model]
     return {"value": round(ups / 1e9, 4), "unit": "G/s", "cores": threads, "kind": "oracle",
-            "sample": f"{host_cpu_model()}: {n_chains} chains x {sweeps} recorded sweeps of "
-                      f"{['Ising', str(prob.q) + '-state Potts', 'multimagnetic Ising'][prob.model]} L={prob.L} "
-                      f"({n_chains * sweeps * prob.N:.3g} updates, {dt:.1f} s)"}
+            "sample": f"{host_cpu_model()}, {threads} threads (the process may use {usable} of the {reported} "
+                      f"cores the machine reports; one GPU's share of the host is 16): {n_chains} chains x "
+                      f"{sweeps} recorded sweeps of {name} L={prob.L} ({n_chains * sweeps * prob.N:.3g} updates, "
+                      f"{dt:.1f} s)",
+            "single_core": {"value": round(ups1 / 1e9, 4), "unit": "G/s", "cores": 1,
+                            "sample": f"{single_chains} chains x {sweeps} sweeps on one thread "
+                                      f"({single_chains * sweeps * prob.N:.3g} updates, {dt1:.1f} s)"},
+            "nproc": reported, "usable_cores": usable}
 
 
 OPS_PER_POTTS_UPDATE = 62   # half a Philox block, the proposal and twice the compares
@@ -138,7 +176,8 @@ def main():
     ap.add_argument("--fixed", action="store_true",
                     help="skip tuning: 16 chains per workgroup, 3 producer waves, LDS placement")
     ap.add_argument("--no-extra", action="store_true", help="skip the production and reweighting leg")
-    ap.add_argument("--workload", default="ising64", choices=["ising64", "potts32", "mixed", "mag32"])
+    ap.add_argument("--workload", default="ising64",
+                    choices=["ising64", "potts32", "mixed", "mag32", "ising96", "ising128", "potts48"])
     ap.add_argument("--graph", action="store_true", help="run each iteration as one HIP graph launch")
     ap.add_argument("--scan-chains", type=int, default=0, metavar="L",
                     help="instead of the benchmark: sweep throughput of an L x L lattice versus the number of chains")
@@ -171,10 +210,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    plan = {"ising64": C2, "potts32": C3, "mixed": C4, "mag32": C_MAG}[args.workload]
-    probs = list(plan.problems)
+    if args.workload in ("ising96", "ising128", "potts48"):
+        # the learned-initial-weights test sizes: 8192 chains, 2000 sweeps per iteration
+        from workloads import C5_TEST_CHAINS, POTTS
+        L = int(args.workload[-3:] if args.workload.endswith("128") else args.workload[-2:])
+        model = POTTS if args.workload.startswith("potts") else ISING
+        probs = [Problem(model, L, C5_TEST_CHAINS, 1, q=(8 if model == POTTS else 2))]
+        M = 2000
+    else:
+        plan = {"ising64": C2, "potts32": C3, "mixed": C4, "mag32": C_MAG}[args.workload]
+        probs = list(plan.problems)
+        M = plan.sweeps_per_iter
     prob = probs[0]
-    M = plan.sweeps_per_iter
     torch.cuda.set_device(0)
     opts = dict(rng_mode=args.rng_mode, chains_per_wg=args.chains_per_wg, use_graph=int(args.graph))
     if args.fixed:
@@ -182,7 +229,9 @@ def main():
     ctx = pm.Muca(probs, device="cuda:0", **opts)
     launch = [ctx.launch_info(i) for i in range(len(probs))]
     updates_per_step = sum(p.n_chains * p.N for p in probs) * M
-    ops_per_update = OPS_PER_ISING_UPDATE if args.workload in ("ising64", "mag32") else None
+    single_model = len(probs) == 1
+    potts_model = single_model and prob.model == 1
+    ops_per_update = (OPS_PER_POTTS_UPDATE if potts_model else OPS_PER_ISING_UPDATE) if single_model else None
 
     def step():
         if args.graph:
@@ -205,10 +254,6 @@ def main():
 
     value = updates_per_step * args.steps / dt / 1e9
     kernel_rate = updates_per_step / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    if ops_per_update is None:
-        # Potts: half a Philox block (40 ops) plus the update (8 compares,
-        # 6 adds, proposal 3, table index 2, compare 1, state 2) = 62
-        ops_per_update = 62 if args.workload == "potts32" else None
     achieved = (ops_per_update or 0) * updates_per_step / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
 
     extra = {}
@@ -234,7 +279,21 @@ def main():
                  "one weight iteration of 2000 sweeps",
         "mag32": "multimagnetic 2D Ising L=32 at beta = 1.5 beta_0 (weights over M), 4096 chains, one weight "
                  "iteration of 2000 sweeps (sweep + merge + recursion + tables)",
+        "ising96": "2D Ising L=96 periodic, 8192 chains, one weight iteration of 2000 sweeps from lnW = 0",
+        "ising128": "2D Ising L=128 periodic, 8192 chains, one weight iteration of 2000 sweeps from lnW = 0",
+        "potts48": "2D 8-state Potts L=48 periodic, 8192 chains, one weight iteration of 2000 sweeps from lnW = 0",
     }[args.workload]
+    # the serial chain's ceiling: one table-read latency per site and chain
+    chains = sum(p.n_chains for p in probs)
+    ceiling_ups = chains * CLOCK_HZ / LDS_LATENCY_CYCLES
+    serial = None
+    if ops_per_update:
+        serial = {"Gups": round(ceiling_ups / 1e9, 1),
+                  "frac": round(min(1.0, ceiling_ups * ops_per_update / PEAK_INT32_OPS), 4),
+                  "achieved_over_ceiling": round(kernel_rate * 1e9 / ceiling_ups, 3),
+                  "note": f"{chains} chains x {CLOCK_HZ / 1e9} GHz / {LDS_LATENCY_CYCLES} cycles: every update "
+                          "waits for the table entry its chain's previous update selected, so this many chains "
+                          "cannot exceed this rate or this fraction of the ALU peak with sequential sweeps"}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "G/s", "n_gpus": 1,
@@ -247,14 +306,17 @@ def main():
                      "unit": "Tops/s (int32 lane ops)", "frac": round(achieved / PEAK_INT32_OPS, 5),
                      "traffic": measured_traffic(updates_per_step) if args.workload == "ising64" else None,
                      "kernel": "sweep_kernel", "kernel_avg_ms": round(avg_ms, 3), "kernel_launches": n_launch,
-                     "kernel_rate_Gups": round(kernel_rate, 3), "ops_per_update": ops_per_update},
+                     "kernel_rate_Gups": round(kernel_rate, 3), "ops_per_update": ops_per_update,
+                     "ops_derivation": OPS_DERIVATION["potts" if potts_model else "ising"] if single_model else None,
+                     "serial_chain_ceiling": serial},
         "extra": dict(extra, last_iter={k: stats[k] for k in ("k_lo", "k_hi", "visited", "reachable", "flat")},
                       kernel_source_hash=kernel_source_hash()),
     }
     ctx.close()
     if not args.no_cpu:
-        # about 10-15 s of the oracle on 16 host threads
-        out["cpu_baseline"] = cpu_baseline(prob, 2000, 2048 if prob.model != 1 else 4096)
+        # about 10-15 s of the oracle on 16 host threads, then about 8 s on one
+        big = prob.model != 1
+        out["cpu_baseline"] = cpu_baseline(prob, 2000, 2048 if big else 4096, 96 if big else 192)
     print(json.dumps(out), flush=True)
 
 

@@ -141,7 +141,8 @@ typedef struct {
     int32_t pad1;
 } muca_launch_info;
 
-/* Bytes of device workspace that mucaInit needs for these problems. */
+/* Bytes of device workspace that mucaInit needs for these problems.  (Not a
+ * step of the method: memory planning of this library.) */
 muca_status mucaWorkspaceSize(const muca_problem *problems, int32_t n_problems,
                               const muca_options *opts, size_t *bytes);
 
@@ -155,13 +156,20 @@ muca_status mucaInit(muca_ctx *out, const muca_problem *problems, int32_t n_prob
                      void *hip_stream);
 
 /* Replaces lnW of problem prob (n_bins = 2N+1 host doubles, copied) and
- * rebuilds its table. */
+ * rebuilds its table: installs the weights W(E) of Eq. (1) directly, for
+ * example a canonical exp(-beta E) or an estimate of 1/Omega that starts the
+ * recursion of Sec. 2 elsewhere than at W = 1.  MUCA_EINVAL for a wrong n_bins
+ * or a value that is not finite.  Synchronises. */
 muca_status mucaSetLogWeights(muca_ctx ctx, int32_t prob, const double *lnW, int32_t n_bins);
 
 /* Runs n_sweeps sweeps of every chain of every problem (Sec. 3), asynchronously
  * on the stream.  record: MUCA_REC_NONE (thermalisation), MUCA_REC_MUCA
  * (one histogram count per chain per sweep), MUCA_REC_PROD (count and |M|
- * per chain per sweep). */
+ * per chain per sweep).  One call is one kernel launch, whose walkers count
+ * its chunks of sites in 32 bits: MUCA_EINVAL, before anything is enqueued,
+ * for n_sweeps > 2^30 or more sweeps than (2^31 - 1) / (chunks per sweep)
+ * (chunks of 32 to 72 sites; for example 2^25 - 1 sweeps at Ising L = 64 with
+ * the byte walker); MUCA_ESTATE if the 32-bit sweep counter would wrap. */
 muca_status mucaSweep(muca_ctx ctx, int64_t n_sweeps, int32_t record);
 
 /* Bins: "k" below stands for the problem's bin index (m for MUCA_ISING_MAG).
@@ -174,7 +182,8 @@ muca_status mucaMergeUpdate(muca_ctx ctx, int32_t update, muca_iter_stats *out);
 
 /* One weight iteration: n_sweeps recorded sweeps, merge, recursion, new
  * tables (Fig. 1's loop body).  With use_graph the whole iteration is one
- * HIP graph launch.  Synchronises the stream; out as in mucaMergeUpdate. */
+ * HIP graph launch.  Synchronises the stream; out as in mucaMergeUpdate.
+ * n_sweeps is limited as in mucaSweep. */
 muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out);
 
 /* Time-series reweighting, Eq. (2), of the production data of problem prob
@@ -186,7 +195,10 @@ muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out);
 muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_t n_betas,
                          double *e_per_site, double *c_v, double *abs_m_per_site);
 
-/* Zeroes the per-chain production accumulators of every problem. */
+/* Zeroes the per-chain production accumulators of every problem: starts a
+ * new set of production measurements for Eq. (2) (Sec. 3 thermalises again
+ * before production; the caller runs MUCA_REC_NONE sweeps for that).
+ * Synchronises. */
 muca_status mucaClearProduction(muca_ctx ctx);
 
 /* Order-disorder interface tension from a reweighted energy histogram
@@ -231,11 +243,17 @@ muca_status mucaEqualHeight(int32_t model, int32_t L, const double *lnW, const i
 muca_status mucaInterfaceTension(muca_ctx ctx, int32_t prob, double beta_lo, double beta_hi, double *beta_eqh,
                                  double *sigma_od, int32_t *k_peaks, double *lnP);
 
-/* Copies state of problem prob to host memory (bytes must match exactly):
+/* Copies state of problem prob to host memory (bytes must match exactly).
+ * Inspection of the sampler's state; not a step of the method.  MUCA_EINVAL
+ * for an unknown item or a byte count that differs from the item's size:
  *   MUCA_GET_H        int64[2N+1]      merged histogram of the last merge
  *   MUCA_GET_LNW      double[2N+1]     current log-weights
- *   MUCA_GET_T        uint32[2N+1][9]  table, column dk+4, dk = -4..4
- *                                      (targets outside 0..2N hold 0)
+ *   MUCA_GET_T        the acceptance table as the walkers read it, copied
+ *                     back from device memory (entries as in the conventions;
+ *                     targets outside the bin range hold 0):
+ *                       Ising uint32[N+1][5], row k/2, column dk/2 + 2
+ *                       (dk = -4..4 in steps of 2; odd k never occurs)
+ *                       Potts uint32[2N+1][9], row k, column dk + 4
  *   MUCA_GET_SPINS    uint8[N][C]      spins, site-major, chain fastest
  *                                      (Ising 0/1 for s = -1/+1, Potts 0..q-1)
  *   MUCA_GET_K        int32[C]         unsatisfied bonds per chain
@@ -246,7 +264,7 @@ muca_status mucaInterfaceTension(muca_ctx ctx, int32_t prob, double beta_lo, dou
  *   MUCA_GET_SWEEP    uint32[1]        sweeps done since init
  *   MUCA_GET_REACH    uint8[2N+1]      reachable-bin mask
  * For MUCA_ISING_MAG every per-bin item has N+1 bins (m = 0..N), T is
- * uint32[N+1][10] with column j + 5u (u = 1 when the spin to flip is up, so
+ * uint32[N+1][10], row m, column j + 5u (u = 1 when the spin to flip is up, so
  * that m' = m - 1, else m' = m + 1; the flip changes k by dk = 2j - 4), and
  * MUCA_GET_PROD_ABSM holds the sums of k (unsatisfied bonds) per m.
  * Synchronises the stream. */
@@ -257,25 +275,30 @@ enum {
 };
 muca_status mucaGet(muca_ctx ctx, int32_t what, int32_t prob, void *host_dst, size_t bytes);
 
-/* Launch configuration chosen for problem prob. */
+/* Launch configuration chosen for problem prob (by this library's tuner; not
+ * in the paper). */
 muca_status mucaLaunchInfo(muca_ctx ctx, int32_t prob, muca_launch_info *info);
 
 /* Average duration in milliseconds of the sweep-kernel launches enqueued by
  * mucaSweep / mucaIterate since the last call (HIP events on the context's
- * stream), and how many launches it covers.  Synchronises. */
+ * stream), and how many launches it covers.  Synchronises.  (Measurement of
+ * this library; not in the paper.) */
 muca_status mucaSweepTiming(muca_ctx ctx, double *avg_ms, int32_t *n_launches);
 
 /* Checkpoint of the whole sampling state (spins, k, M, sweep counter, lnW,
- * per-chain histograms) into a caller-owned host buffer.  With blob == NULL
+ * per-chain histograms) into a caller-owned host buffer (resuming a run is not
+ * a step of the method; the paper does not describe one).  With blob == NULL
  * only *bytes is set.  mucaRestore loads such a blob into a context created
  * with the same problems; the continued run equals an uninterrupted one bit
  * for bit.  Both synchronise.  Errors: MUCA_EINVAL for a buffer too small, a
- * blob of another size or context, or a spin outside 0..q-1, all found before
- * any state changes (k and M are recomputed from the spins, not read). */
+ * blob of another size or context, a spin outside 0..q-1 or a log-weight that
+ * is not finite, all found before any state changes (k and M are recomputed
+ * from the spins, not read). */
 muca_status mucaCheckpoint(muca_ctx ctx, void *blob, size_t *bytes);
 muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes);
 
-/* The problem definition of index prob (as validated, q = 2 for Ising). */
+/* The problem definition of index prob (as validated, q = 2 for Ising).  Not
+ * a step of the method. */
 muca_status mucaProblemInfo(muca_ctx ctx, int32_t prob, muca_problem *out);
 
 /* ---------------------------------------------------------------------
@@ -320,7 +343,8 @@ muca_status mucaMlpSetLogWeights(muca_mlp m, muca_ctx ctx, int32_t prob);
 void mucaMlpDestroy(muca_mlp m);
 const char *mucaMlpLastError(muca_mlp m);
 
-/* Frees the context (not the workspace).  Safe on NULL. */
+/* Frees the context (not the workspace).  Safe on NULL.  Not a step of the
+ * method. */
 void mucaDestroy(muca_ctx ctx);
 
 /* Last error text of ctx (or of the last failed mucaInit when ctx is NULL). */

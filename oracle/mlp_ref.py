@@ -9,7 +9,9 @@ HIP kernels; with rounding off the function is the exact float64 network.
 Pins: the float64 gradient against central finite differences, the rounding
 against hand-worked bfloat16 cases, GELU against the exact x*Phi(x) within the
 tanh form's error, and Adam (Kingma and Ba) against the closed forms of its
-first step, of a constant gradient and of a single impulse.
+first step, of a constant gradient and of a single impulse.  term_scales (the
+yardstick of the element-wise comparison, not a result) is pinned by the
+triangle inequality and by equality when every term is non-negative.
 
 Parameter vector layout (8705 floats): W1[64][4], b1[64], W2[64][64], b2[64],
 W3[64][64], b3[64], W4[64], b4[1].
@@ -80,6 +82,30 @@ def loss_and_grad(p, x, t, round_bf16=True):
     g["W1"] = G1.T @ c["x0"]
     g["b1"] = G1.sum(axis=0)
     return loss, pack(g)
+
+
+def term_scales(p, x, t, round_bf16=True):
+    """For every output y[s] and every gradient element: the sum of the
+    absolute values of the terms that element sums (|b4| + sum_i |W4_i a3_si|
+    for y; sum_s |G_so a_si| for a weight gradient, sum_s |G_so| for a bias
+    gradient, with the pre-activation gradients G at the same rounding as
+    loss_and_grad).  A sum of K terms evaluated in another order or precision
+    differs from the exact sum by at most a multiple of this scale, so it is
+    the yardstick of an element-wise comparison.  Returns (y_scale, g_scale)."""
+    R = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    y, c = forward(p, x, round_bf16)
+    w = c["w"]
+    n = y.shape[0]
+    dy = 2.0 * (y - t) / n
+    ys = np.abs(w["b4"][0]) + np.abs(c["a3"]) @ np.abs(w["W4"])
+    G3 = R(dy[:, None] * w["W4"][None, :] * gelu(c["z3"])[1])
+    G2 = R((G3 @ w["W3"]) * gelu(c["z2"])[1])
+    G1 = R((G2 @ w["W2"]) * gelu(c["z1"])[1])
+    s = dict(W4=np.abs(c["a3"]).T @ np.abs(dy), b4=np.array([np.abs(dy).sum()]),
+             W3=np.abs(G3).T @ np.abs(c["a2"]), b3=np.abs(G3).sum(axis=0),
+             W2=np.abs(G2).T @ np.abs(c["a1"]), b2=np.abs(G2).sum(axis=0),
+             W1=np.abs(G1).T @ np.abs(c["x0"]), b1=np.abs(G1).sum(axis=0))
+    return ys, pack(s)
 
 
 def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

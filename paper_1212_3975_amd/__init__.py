@@ -252,8 +252,13 @@ class Muca:
         return self._get(GET_LNW, prob, np.float64, self._dims(prob)[1])
 
     def table(self, prob=0):
-        cols = 10 if self.problems[prob].model == ISING_MAG else 9
-        return self._get(GET_T, prob, np.uint32, (self._dims(prob)[1], cols))
+        """The device acceptance table: Ising [N+1][5] (row k/2, column
+        dk/2 + 2), Potts [2N+1][9] (row k, column dk + 4), multimagnetic
+        [N+1][10] (row m, column j + 5u)."""
+        p = self.problems[prob]
+        N = p.L * p.L
+        shape = {ISING: (N + 1, 5), POTTS: (2 * N + 1, 9), ISING_MAG: (N + 1, 10)}[p.model]
+        return self._get(GET_T, prob, np.uint32, shape)
 
     def spins(self, prob=0):
         """Spins as [C][N] (chain-major) for comparison; the device keeps [N][C]."""

@@ -416,6 +416,26 @@ bool fits(muca_ctx ctx, const ProbHost &h, int cw, int spin_lds, int table_lds, 
     return lds_bytes_for(d, it, nprod) <= ctx->max_lds;
 }
 
+// The walkers count a launch's chunks in int32: the longest launch the
+// current configuration allows.
+int64_t max_sweeps_per_launch(muca_ctx ctx) {
+    int64_t worst = 1;
+    for (const WorkItem &it : ctx->items)
+        worst = std::max<int64_t>(worst, chunks_per_sweep(ctx->h_probdev[it.prob], it, ctx->n_producer_waves));
+    return (int64_t)INT32_MAX / worst;
+}
+
+muca_status check_sweeps(muca_ctx ctx, int64_t n_sweeps) {
+    if (n_sweeps > (1 << 30)) return fail(ctx, MUCA_EINVAL, "n_sweeps out of range");
+    const int64_t cap = max_sweeps_per_launch(ctx);
+    if (n_sweeps > cap)
+        return fail(ctx, MUCA_EINVAL, "n_sweeps %lld exceeds %lld, the most one launch of this configuration counts",
+                    (long long)n_sweeps, (long long)cap);
+    if ((uint64_t)ctx->sweep + (uint64_t)n_sweeps > 0xFFFFFFFFull)
+        return fail(ctx, MUCA_ESTATE, "sweep counter would wrap");
+    return MUCA_OK;
+}
+
 muca_status enqueue_sweep(muca_ctx ctx, int64_t n_sweeps, int record, bool timed) {
     SweepLaunch l;
     l.probs = ctx->d_probs;
@@ -894,14 +914,14 @@ muca_status mucaSetLogWeights(muca_ctx ctx, int32_t prob, const double *lnW, int
 
 muca_status mucaSweep(muca_ctx ctx, int64_t n_sweeps, int32_t record) {
     if (!ctx) return MUCA_EINVAL;
-    if (n_sweeps < 0 || n_sweeps > (1 << 30)) return fail(ctx, MUCA_EINVAL, "n_sweeps out of range");
+    if (n_sweeps < 0) return fail(ctx, MUCA_EINVAL, "n_sweeps out of range");
     if (record < 0 || record > 2) return fail(ctx, MUCA_EINVAL, "record must be 0, 1 or 2");
     if (record == kRecProd && !ctx->probs[0].prod_alloc)
         return fail(ctx, MUCA_ESTATE, "context was created without production accumulators");
     if (n_sweeps == 0) return MUCA_OK;
-    if ((uint64_t)ctx->sweep + (uint64_t)n_sweeps > 0xFFFFFFFFull)
-        return fail(ctx, MUCA_ESTATE, "sweep counter would wrap");
-    muca_status st = enqueue_sweep(ctx, n_sweeps, record, true);
+    muca_status st = check_sweeps(ctx, n_sweeps);
+    if (st) return st;
+    st = enqueue_sweep(ctx, n_sweeps, record, true);
     if (st) return st;
     HIPCHECK(ctx, launch_advance(ctx->d_sweep, (uint32_t)n_sweeps, ctx->stream));
     ctx->sweep += (uint32_t)n_sweeps;
@@ -928,9 +948,9 @@ muca_status mucaMergeUpdate(muca_ctx ctx, int32_t update, muca_iter_stats *out) 
 
 muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out) {
     if (!ctx) return MUCA_EINVAL;
-    if (n_sweeps <= 0 || n_sweeps > (1 << 30)) return fail(ctx, MUCA_EINVAL, "n_sweeps out of range");
-    if ((uint64_t)ctx->sweep + (uint64_t)n_sweeps > 0xFFFFFFFFull)
-        return fail(ctx, MUCA_ESTATE, "sweep counter would wrap");
+    if (n_sweeps <= 0) return fail(ctx, MUCA_EINVAL, "n_sweeps out of range");
+    muca_status cs = check_sweeps(ctx, n_sweeps);
+    if (cs) return cs;
     if (!ctx->opt.use_graph) {
         muca_status st = mucaSweep(ctx, n_sweeps, kRecMuca);
         if (st) return st;
@@ -1063,21 +1083,10 @@ muca_status mucaGet(muca_ctx ctx, int32_t what, int32_t prob, void *dst, size_t 
         std::memcpy(dst, p.lnW.data(), 8 * nb);
         return MUCA_OK;
     case MUCA_GET_T: {
-        if (p.def.model == MUCA_ISING_MAG) {
-            if ((st = need(4 * nb * 10))) return st;
-            HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
-            device_table(p, (uint32_t *)dst);   // the device layout is [m][10] already
-            return MUCA_OK;
-        }
-        if ((st = need(4 * nb * 9))) return st;
-        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
-        uint32_t *T = (uint32_t *)dst;
-        for (int k = 0; k < (int)nb; ++k)
-            for (int j = 0; j < 9; ++j) {
-                const int t = k + j - 4;
-                T[(size_t)k * 9 + j] = (t >= 0 && t < (int)nb) ? threshold(p.lnW[t] - p.lnW[k]) : 0u;
-            }
-        return MUCA_OK;
+        // the words the walkers read: this problem's device table, copied back
+        const size_t words = (size_t)p.trows * p.tcols;
+        if ((st = need(4 * words))) return st;
+        return d2h(d.table, 4 * words);
     }
     case MUCA_GET_SPINS:
         if ((st = need((size_t)p.N * C))) return st;
@@ -1224,6 +1233,15 @@ muca_status mucaRestore(muca_ctx ctx, const void *blob, size_t bytes) {
             if (sp[i] >= q)
                 return fail(ctx, MUCA_EINVAL, "checkpoint spin %u out of range 0..%u in problem %zu", (unsigned)sp[i],
                             (unsigned)(q - 1), (size_t)(&p - ctx->probs.data()));
+        // log-weights feed the thresholds: a NaN or an infinity has no threshold
+        const uint8_t *lw = sp + ns + 8 * C;
+        for (int k = 0; k < p.nbins; ++k) {
+            double v;
+            std::memcpy(&v, lw + 8 * (size_t)k, 8);
+            if (!std::isfinite(v))
+                return fail(ctx, MUCA_EINVAL, "checkpoint lnW[%d] of problem %zu is not finite", k,
+                            (size_t)(&p - ctx->probs.data()));
+        }
         scan += sizeof(muca_problem) + ns + 8 * C + 8 * (size_t)p.nbins + 4 * (size_t)p.nbins * C;
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));

@@ -65,6 +65,9 @@ struct SweepLaunch {
 
 // LDS bytes one work item needs (table, lattice, random-word ring).
 int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves);
+// Chunks per sweep of the walker that runs this work item; a launch of S
+// sweeps counts S times this many chunks in an int32.
+int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves);
 // Whether the sweep kernel takes the fast Ising walker for this problem.
 bool uses_fast_walker(const ProbDev &p, int n_producer_waves);
 // Raises the dynamic-LDS limit of the sweep kernel.

@@ -154,6 +154,17 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     return lds_plan(p, it, n_producer_waves).total;
 }
 
+// Chunks one sweep of this work item takes in the walker that runs it (the
+// unit of the walkers' int32 loop counters).
+int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
+    if (fast_ising_ok(p, n_producer_waves)) {
+        if (p.model == kIsing && packed_ising(p, it)) return 64 * 16 / kPackedChunkDwords;
+        return p.L / fast_rows_per_chunk(p.L);
+    }
+    if (fast_potts_ok(p, n_producer_waves)) return p.L / potts_rows_per_chunk(p.L, potts_wide(it.nchains));
+    return (p.N + kChunkSites - 1) / kChunkSites;
+}
+
 // The fast Ising walker (and its multimagnetic variant) has compiled shapes
 // for these sizes and needs both
 // arrays in LDS and producer waves.

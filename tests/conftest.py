@@ -24,6 +24,13 @@ def gpu_available() -> bool:
         return False
 
 
+def device_table(orc):
+    """The oracle's acceptance table in the library's device layout: Ising
+    keeps the rows of even k and the columns of even dk ([N+1][5]); Potts and
+    the multimagnetic table are laid out alike already."""
+    return orc.T[::2, ::2] if orc.model == 0 else orc.T
+
+
 @pytest.fixture(scope="session")
 def oracle_lib():
     import oracle

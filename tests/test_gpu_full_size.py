@@ -1,15 +1,27 @@
 """Parity at the full sizes of the benchmark workloads, in the launch
-configuration the benchmark uses (tuned).  The oracle recomputes a sample of
-chains one by one (a chain's trajectory depends only on the seed, its index
-and lnW); everything else is checked through properties that hold at any
-size: tracked energies equal a recompute from the spins, the merged histogram
-sums to chains x sweeps and is empty on unreachable bins."""
+configuration the benchmark uses (tuned).
+
+- Ising L = 64 and 8-state Potts L = 32 with 4096 chains: the oracle runs
+  every chain through two weight iterations with its own recursion.  The
+  first iteration starts from lnW = 0 (where every Ising move is accepted);
+  the second is the first under real weights.  Per-chain and merged
+  histograms, spins, energies, weights (as bits) and tables match bit for
+  bit after each.
+- Reweighting (Eq. 2) of an Ising L = 64 production over more than 256 bins
+  with data (each thread of the reweighting kernel then sums several bins),
+  against the oracle's production and reweighting at 1e-10 relative.
+- The learned-init test sizes (Ising L = 96, 128 and 8-Potts L = 48 with 8192
+  chains) under canonical weights installed through the ABI: sampled chains
+  recomputed one by one by the oracle, the rest through properties that hold
+  at any size.
+- The nine-problem batch in one launch, sampled chains.
+"""
 import numpy as np
 import pytest
 
 import oracle
-from conftest import gpu_available
-from workloads import C2, C3
+from conftest import device_table, gpu_available
+from workloads import C2, C3, ISING, POTTS, Problem
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -19,38 +31,101 @@ def _recompute_k(spins_cn: np.ndarray, L: int) -> np.ndarray:
     return ((s != np.roll(s, 1, axis=2)).sum(axis=(1, 2)) + (s != np.roll(s, 1, axis=1)).sum(axis=(1, 2))).astype(np.int32)
 
 
+def _same_bits(a, b):
+    return np.array_equal(np.asarray(a, np.float64).view(np.uint64), np.asarray(b, np.float64).view(np.uint64))
+
+
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("plan", [C2, C3], ids=["ising64x4096", "potts32x4096"])
-def test_first_iteration_sampled_chains(plan):
+def test_two_iterations_every_chain_bit_exact(plan):
     import paper_1212_3975_amd as pm
     prob = plan.problems[0]
     M = plan.sweeps_per_iter
     with pm.Muca([prob]) as ctx:
         print("launch", ctx.launch_info(), flush=True)
-        ctx.sweep(M, pm.REC_MUCA)
+        orc = oracle.OracleRun(prob.model, prob.L, prob.n_chains, prob.seed, q=prob.q)
+        print(f"  oracle threads {orc.n_threads}", flush=True)
+        for it in range(2):
+            ctx.sweep(M, pm.REC_MUCA)
+            ch = ctx.chain_hist()
+            st = ctx.merge_update(True)[0]
+            print(f"  iteration {it}: library done, oracle running", flush=True)
+            H, fl, per_chain = orc.iterate(M)
+            print(f"  iteration {it}: visited {fl.visited} bins in k = {fl.k_lo}..{fl.k_hi}", flush=True)
+            assert np.array_equal(ch, per_chain), f"per-chain histograms differ at iteration {it}"
+            assert np.array_equal(ctx.H(), H), f"merged H differs at iteration {it}"
+            assert st["total"] == prob.n_chains * M and bool(st["flat"]) == fl.flat
+            assert (st["k_lo"], st["k_hi"], st["visited"]) == (fl.k_lo, fl.k_hi, fl.visited)
+            assert _same_bits(ctx.lnW(), orc.lnW), f"lnW differs at iteration {it}"
+            assert np.array_equal(ctx.table(), device_table(orc)), f"T differs at iteration {it}"
+            assert np.array_equal(ctx.spins(), orc.spins), f"spins differ at iteration {it}"
+            assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
+        # the second iteration ran under weights that reject moves
+        T = device_table(orc)
+        assert np.count_nonzero((T != 0) & (T != 0xFFFFFFFF)) > 100
+        assert np.array_equal(_recompute_k(ctx.spins(), prob.L), ctx.k())
+
+
+@pytest.mark.timeout(600)
+def test_reweighting_over_thousands_of_bins():
+    """Ising L = 64 (8193 bins), 256 chains: eight weight iterations with the
+    correction function widen the sampled range, then 500 unrecorded and 1000
+    production sweeps.  Counts and |M| sums are bit-exact and Eq. (2) on 200
+    beta in [0.3, 0.6] matches the oracle to 1e-10 relative."""
+    import paper_1212_3975_amd as pm
+    prob = Problem(ISING, 64, 256, 77)
+    with pm.Muca([prob], correction=1) as ctx:
+        print("launch", ctx.launch_info(), flush=True)
+        orc = oracle.OracleRun(prob.model, prob.L, prob.n_chains, prob.seed)
+        for it in range(8):
+            st = ctx.iterate(1000)[0]
+            H, fl, _ = orc.iterate(1000, correct=True)
+            print(f"  iteration {it}: visited {fl.visited}", flush=True)
+            assert np.array_equal(ctx.H(), H) and st["visited"] == fl.visited
+            assert _same_bits(ctx.lnW(), orc.lnW), f"lnW differs at iteration {it}"
+        ctx.clear_production()
+        ctx.sweep(500, pm.REC_NONE)
+        ctx.sweep(1000, pm.REC_PROD)
+        cnt, sab = orc.production(500, 1000)
+        assert np.count_nonzero(cnt) > 256, np.count_nonzero(cnt)
+        print(f"  production over {np.count_nonzero(cnt)} bins", flush=True)
+        assert np.array_equal(ctx.prod_counts(), cnt) and np.array_equal(ctx.prod_absm(), sab)
+        betas = np.array(C2.betas)
+        e, c, m = ctx.reweight(0, betas)
+        eo, co, mo = oracle.reweight(prob.model, prob.L, orc.lnW, cnt, sab, betas)
+        for got, want in ((e, eo), (c, co), (m, mo)):
+            rel = np.abs(got - want) / np.abs(want)
+            assert np.all(rel <= 1e-10), float(rel.max())
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prob,beta", [(Problem(ISING, 96, 8192, 1), 0.42), (Problem(ISING, 128, 8192, 2), 0.42),
+                                       (Problem(POTTS, 48, 8192, 3, q=8), 1.30)],
+                         ids=["ising96x8192", "ising128x8192", "potts48x8192"])
+def test_learned_init_sizes_sampled_chains(prob, beta):
+    """Canonical weights lnW = -beta E (acceptance below one for every uphill
+    move) through the ABI; 200 sweeps from the infinite-temperature start."""
+    import paper_1212_3975_amd as pm
+    lnW = -beta * oracle.energies(prob.model, prob.L)
+    with pm.Muca([prob]) as ctx:
+        print("launch", ctx.launch_info(), flush=True)
+        ctx.set_log_weights(0, lnW)
+        ctx.sweep(200, pm.REC_MUCA)
         ch = ctx.chain_hist()
         spins = ctx.spins()
         k = ctx.k()
-        for c0, n in ((0, 32), (prob.n_chains - 32, 32)):
+        for c0, n in ((0, 24), (prob.n_chains // 2 + 5, 8), (prob.n_chains - 24, 24)):
             print(f"  oracle chains {c0}..{c0 + n - 1}", flush=True)
             orc = oracle.OracleRun(prob.model, prob.L, n, prob.seed, q=prob.q, chain0=c0)
-            orc.sweeps(M, oracle.REC_MUCA)
+            orc.set_log_weights(lnW)
+            orc.sweeps(200, oracle.REC_MUCA)
             assert np.array_equal(ch[c0:c0 + n], orc.hist)
             assert np.array_equal(spins[c0:c0 + n], orc.spins)
             assert np.array_equal(k[c0:c0 + n], orc.k)
         assert np.array_equal(_recompute_k(spins, prob.L), k)
-        st = ctx.merge_update(True)[0]
-        H = ctx.H()
-        assert H.sum() == prob.n_chains * M == st["total"]
-        assert np.all(H[~ctx.reachable()] == 0)
-        assert np.array_equal(H, ch.astype(np.int64).sum(axis=0))
-        # the weights follow the recursion from lnW = 0 on the merged histogram
-        lnW = ctx.lnW()
-        assert np.all(lnW[H == 0] == 0.0) and np.all(lnW[H > 0] <= 0.0)
-        # a second iteration under the new weights keeps every invariant
-        st2 = ctx.iterate(M)[0]
-        assert st2["total"] == prob.n_chains * M
-        assert np.array_equal(_recompute_k(ctx.spins(), prob.L), ctx.k())
-        assert np.all(ctx.H()[~ctx.reachable()] == 0)
+        assert np.array_equal(ch.sum(axis=1), np.full(prob.n_chains, 200))
+        # the chains have cooled from k ~ N (random spins) under the weights
+        assert k.mean() < 0.8 * prob.L * prob.L * (1 if prob.model == ISING else 2)
 
 
 def test_mixed_batch_one_launch_sampled_chains():

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from conftest import gpu_available
+from conftest import device_table, gpu_available
 from workloads import C1, ISING, ISING_MAG, POTTS, Problem
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -55,7 +55,7 @@ def _compare_iterations(ctx, orc, n_iters, n_sweeps, prob_idx=0, check_chain_his
         assert bool(stats["flat"]) == fl.flat and bool(stats["covered"]) == fl.covered
         assert stats["total"] == orc.n_chains * n_sweeps
         assert _same_bits(ctx.lnW(prob_idx), orc.lnW), f"lnW differs at iteration {it}"
-        assert np.array_equal(ctx.table(prob_idx), orc.T), f"T differs at iteration {it}"
+        assert np.array_equal(ctx.table(prob_idx), device_table(orc)), f"T differs at iteration {it}"
         assert np.array_equal(ctx.spins(prob_idx), orc.spins), f"spins differ at iteration {it}"
         assert np.array_equal(ctx.k(prob_idx), orc.k), f"k differs at iteration {it}"
         assert np.array_equal(ctx.m(prob_idx), orc.m), f"M differs at iteration {it}"
@@ -70,7 +70,7 @@ def test_initial_state_matches():
             assert np.array_equal(ctx.spins(), orc.spins)
             assert np.array_equal(ctx.k(), orc.k) and np.array_equal(ctx.m(), orc.m)
             assert np.array_equal(ctx.reachable(), orc.mask)
-            assert np.array_equal(ctx.table(), orc.T)
+            assert np.array_equal(ctx.table(), device_table(orc))
 
 
 def test_c1_ising_L8_full_run_bit_exact():
@@ -219,7 +219,7 @@ def test_set_log_weights_canonical_limit():
         ctx.set_log_weights(0, lnW)
         orc = _orc(prob)
         orc.set_log_weights(lnW)
-        assert np.array_equal(ctx.table(), orc.T)
+        assert np.array_equal(ctx.table(), device_table(orc))
         ctx.sweep(500, pm.REC_MUCA)
         orc.sweeps(500, oracle.REC_MUCA)
         assert np.array_equal(ctx.chain_hist(), orc.hist)
@@ -333,7 +333,7 @@ def test_multimagnetic_bit_exact(prob, cfg):
         assert ctx.launch_info()["fast_walker"] == int(placed and prob.L in (16, 24, 32, 48, 64))
         orc = _orc(prob)
         assert ctx.table().shape == (prob.L * prob.L + 1, 10)
-        assert np.array_equal(ctx.table(), orc.T)
+        assert np.array_equal(ctx.table(), device_table(orc))
         assert np.array_equal(ctx.reachable(), orc.mask)
         _compare_iterations(ctx, orc, 4, 150)
 
@@ -353,7 +353,7 @@ def test_multimagnetic_batched_with_energy_models_and_production():
                 assert np.array_equal(ctx.H(j), H)
                 assert _same_bits(ctx.lnW(j), o.lnW)
                 assert np.array_equal(ctx.spins(j), o.spins)
-                assert np.array_equal(ctx.table(j), o.T)
+                assert np.array_equal(ctx.table(j), device_table(o))
         ctx.sweep(100, pm.REC_NONE)
         ctx.sweep(300, pm.REC_PROD)
         cnt, ksum = ctx.prod_counts(0), ctx.prod_absm(0)
@@ -466,3 +466,49 @@ def test_restore_rejects_out_of_range_spins(prob, bad):
             assert np.array_equal(b.spins(), before)
             b.restore(good)
             assert np.array_equal(b.spins(), a.spins()) and np.array_equal(b.k(), a.k())
+
+
+def test_restore_rejects_non_finite_weights():
+    """A checkpoint whose log-weights hold a NaN or an infinity is refused on
+    the host before any state changes."""
+    import ctypes
+    pm = _pm()
+    prob = Problem(ISING, 8, 16, 73)
+    with pm.Muca([prob]) as a:
+        a.iterate(100)
+        good = a.checkpoint()
+        N, C = prob.L * prob.L, prob.n_chains
+        off = 32 + ctypes.sizeof(pm.Problem) + N * C + 8 * C   # header, problem, spins, k and M
+        for bad in (np.nan, np.inf, -np.inf):
+            blob = bytearray(good)
+            blob[off + 8 * 3:off + 8 * 4] = np.float64(bad).tobytes()   # lnW[3]
+            with pm.Muca([prob]) as b:
+                before, w_before = b.spins().copy(), b.lnW().copy()
+                with pytest.raises(pm.MucaError, match="not finite"):
+                    b.restore(bytes(blob))
+                assert np.array_equal(b.spins(), before) and _same_bits(b.lnW(), w_before)
+                b.restore(good)
+                assert _same_bits(b.lnW(), a.lnW())
+
+
+@pytest.mark.parametrize("prob,chunks", [(Problem(ISING, 64, 1, 74), 64), (Problem(ISING, 256, 1, 75), 1024)],
+                         ids=["ising64", "ising256-generic"])
+def test_launch_longer_than_the_chunk_counter_is_refused(prob, chunks):
+    """The walkers count a launch's chunks in int32: a call whose sweeps would
+    overflow that count is refused before any launch, and the sweep counter
+    and the state stay as they were."""
+    pm = _pm()
+    with pm.Muca([prob]) as ctx:
+        info = ctx.launch_info()
+        print("launch", info, flush=True)
+        cap = (2 ** 31 - 1) // chunks
+        ctx.sweep(3, pm.REC_MUCA)
+        before = (ctx.sweep_count(), ctx.spins().copy(), ctx.chain_hist().copy())
+        for call in (lambda: ctx.sweep(cap + 1, pm.REC_MUCA), lambda: ctx.sweep(cap + 1, pm.REC_NONE),
+                     lambda: ctx.iterate(cap + 1)):
+            with pytest.raises(pm.MucaError, match="exceeds"):
+                call()
+        assert ctx.sweep_count() == before[0] == 3
+        assert np.array_equal(ctx.spins(), before[1]) and np.array_equal(ctx.chain_hist(), before[2])
+        with pytest.raises(pm.MucaError, match="out of range"):
+            ctx.sweep(2 ** 30 + 1, pm.REC_NONE)

@@ -110,3 +110,60 @@ def test_adam_impulse_response_decays_at_the_moment_rates():
         c2 = b2 ** (t - 1) * (1 - b2) / (1 - b2 ** t)
         np.testing.assert_allclose(p_new - p, -lr * np.sign(g) * c1 / np.sqrt(c2), rtol=1e-6)
         p = p_new
+
+
+def test_term_scales_bound_the_values_and_equal_them_for_non_negative_terms():
+    """The term scale of every output and gradient element is at least the
+    element's magnitude (triangle inequality), and equals it when every term
+    is non-negative: positive weights, inputs and biases keep every
+    pre-activation and GELU derivative positive, and targets below the
+    predictions make every back-propagated factor positive."""
+    from oracle import mlp_ref
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, (96, 4))
+    t = rng.normal(0, 0.5, 96)
+    p = rng.normal(0, 0.3, mlp_ref.N_PARAMS)
+    ys, gs = mlp_ref.term_scales(p, x, t)
+    y, _ = mlp_ref.forward(p, x)
+    _, g = mlp_ref.loss_and_grad(p, x, t)
+    assert np.all(ys >= np.abs(y) * (1 - 1e-12)) and np.all(gs >= np.abs(g) * (1 - 1e-12))
+    assert np.any(gs > 2 * np.abs(g))   # mixed signs: the bound is not tight
+    p = np.abs(p) + 0.01
+    x = np.abs(x) + 0.01
+    y, _ = mlp_ref.forward(p, x)
+    t = y - 1.0
+    ys, gs = mlp_ref.term_scales(p, x, t)
+    _, g = mlp_ref.loss_and_grad(p, x, t)
+    assert np.allclose(ys, np.abs(y), rtol=1e-12) and np.allclose(gs, np.abs(g), rtol=1e-12)
+
+
+def test_elementwise_check_accepts_rounding_and_rejects_planted_mistakes():
+    """The element-wise check used against the GPU: the reference at float32
+    input precision passes against itself; a reference with a planted
+    mistake (the bias of hidden unit o taken from o+1, two rows of the first
+    16 x 16 tile of W2 swapped, or one sample's input misread) fails."""
+    import mlp_check
+    from oracle import mlp_ref
+    rng = np.random.default_rng(9)
+    n = 300
+    x = np.stack([rng.integers(0, 2, n), rng.integers(0, 2, n), 8.0 / rng.choice([8, 16, 32], n),
+                  rng.uniform(-2, 2, n)], axis=1)
+    t = 0.3 * np.cos(x[:, 3])
+    p = rng.normal(0, 0.25, mlp_ref.N_PARAMS).astype(np.float32).astype(np.float64)
+    y, _ = mlp_ref.forward(p, x)
+    _, g = mlp_ref.loss_and_grad(p, x, t)
+    ys, gs = mlp_ref.term_scales(p, x, t)
+    assert mlp_check.compare(y, y, ys)[0] and mlp_check.compare_grad(g, g, gs)[0]
+    d = mlp_ref.unpack(p)
+    shifted = dict(d, b2=np.roll(d["b2"], -1))
+    swapped = dict(d, W2=d["W2"].copy())
+    swapped["W2"][[3, 4]] = swapped["W2"][[4, 3]]
+    for bad in (mlp_ref.pack(shifted), mlp_ref.pack(swapped)):
+        yb, _ = mlp_ref.forward(bad, x)
+        _, gb = mlp_ref.loss_and_grad(bad, x, t)
+        assert not mlp_check.compare(yb, y, ys)[0]
+        assert not mlp_check.compare_grad(gb, g, gs)[0]
+    xb = x.copy()
+    xb[17, 3] += 0.25
+    yb, _ = mlp_ref.forward(p, xb)
+    assert not mlp_check.compare(yb, y, ys)[0]
