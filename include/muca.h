@@ -195,6 +195,31 @@ muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out);
 muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_t n_betas,
                          double *e_per_site, double *c_v, double *abs_m_per_site);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reweighting of mucaReweight on caller-held production data, with no
+ * context and no allocation.  Its device staging (counts, |M| sums, lnW,
+ * betas, outputs) lives in one static device array of 3,277,568 bytes per
+ * GPU, kept until the process ends; the call allocates nothing.
+ *   model, L     MUCA_ISING (even L, 4..256) or MUCA_POTTS (3..256)
+ *   lnW, cnt     host arrays of n_bins = 2N+1 (log-weights of the production
+ *                run, finite; merged counts, >= 0, not all 0)
+ *   sabs         host int64[n_bins] of merged |M| sums (Ising; ignored and
+ *                may be NULL for Potts)
+ *   betas        host double[n_betas], 1 <= n_betas <= 4096
+ *   outputs      host double[n_betas] each, as mucaReweight
+ *   hip_stream   the stream to run on (NULL = default stream)
+ * Results equal mucaReweight's on the same data bit for bit (same kernel).
+ * Synchronises the stream.  Calls on one GPU share its static array: calls
+ * that overlap in time on one GPU (other threads or streams) race; calls one
+ * after the other do not, since each call writes every entry it reads.
+ * MUCA_EINVAL for bad arguments or sizes beyond the maximum, MUCA_ESTATE for
+ * all-zero counts, MUCA_EHIP for a failed HIP call; text in
+ * mucaLastError(NULL). */
+muca_status mucaReweightStatic(int32_t model, int32_t L, const double *lnW, const int64_t *cnt, const int64_t *sabs,
+                               int32_t n_bins, const double *betas, int32_t n_betas, double *e_per_site,
+                               double *c_v, double *abs_m_per_site, void *hip_stream);
+
 /* Zeroes the per-chain production accumulators of every problem: starts a
  * new set of production measurements for Eq. (2) (Sec. 3 thermalises again
  * before production; the caller runs MUCA_REC_NONE sweeps for that).

@@ -21,7 +21,7 @@ GET_H, GET_LNW, GET_T, GET_SPINS, GET_K, GET_M, GET_CHAIN_H, GET_PROD_CNT, GET_P
 EXPORTED = ["mucaWorkspaceSize", "mucaInit", "mucaSetLogWeights", "mucaSweep", "mucaMergeUpdate",
             "mucaIterate", "mucaReweight", "mucaClearProduction", "mucaGet", "mucaLaunchInfo",
             "mucaSweepTiming", "mucaCheckpoint", "mucaRestore", "mucaProblemInfo", "mucaDestroy", "mucaLastError",
-            "mucaEqualHeight", "mucaInterfaceTension",
+            "mucaEqualHeight", "mucaInterfaceTension", "mucaReweightStatic",
             "mucaMlpWorkspaceSize", "mucaMlpCreate", "mucaMlpSetParams", "mucaMlpGetParams", "mucaMlpClearData",
             "mucaMlpAddData", "mucaMlpAddWeights", "mucaMlpNumSamples", "mucaMlpTrain", "mucaMlpGradients",
             "mucaMlpPredict", "mucaMlpSetLogWeights", "mucaMlpDestroy", "mucaMlpLastError"]
@@ -104,6 +104,8 @@ def lib():
         L.mucaEqualHeight.argtypes = [i32, i32, dp, ctypes.POINTER(ctypes.c_int64), i32, ctypes.c_double,
                                       ctypes.c_double, dp, dp, ip, dp]
         L.mucaInterfaceTension.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double, dp, dp, ip, dp]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.mucaReweightStatic.argtypes = [i32, i32, dp, i64p, i64p, i32, dp, i32, dp, dp, dp, vp]
         fp = ctypes.POINTER(ctypes.c_float)
         L.mucaMlpWorkspaceSize.argtypes = [i32, ctypes.POINTER(sz)]
         L.mucaMlpCreate.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64, vp, sz, vp]
@@ -339,6 +341,29 @@ def equal_height(model: int, L: int, lnW, cnt, beta_lo: float, beta_hi: float):
                                _dptr(lnP, ctypes.c_double))
     _check(rc)
     return {"beta": beta.value, "sigma": sigma.value, "k_peaks": tuple(k3), "lnP": lnP}
+
+
+def reweight_static(model: int, L: int, lnW, cnt, sabs, betas, stream=None):
+    """mucaReweightStatic: Eq. (2) reweighting of caller-held production data
+    (merged counts, |M| sums, log-weights) with no context and no device
+    allocation.  Returns (<E>/N, C_V, <|M|>/N) as float64 arrays."""
+    w = np.ascontiguousarray(lnW, np.float64)
+    c = np.ascontiguousarray(cnt, np.int64)
+    a = None if sabs is None else np.ascontiguousarray(sabs, np.int64)
+    b = np.ascontiguousarray(betas, np.float64)
+    if c.size != w.size or (a is not None and a.size != w.size):
+        raise ValueError("lnW, cnt and sabs differ in size")
+    e, cv, m = (np.zeros(b.size) for _ in range(3))
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    sp = None
+    if stream is not None:
+        sp = ctypes.c_void_p(stream.cuda_stream)
+    rc = lib().mucaReweightStatic(int(model), int(L), _dptr(w, ctypes.c_double), c.ctypes.data_as(i64),
+                                  None if a is None else a.ctypes.data_as(i64), w.size, _dptr(b, ctypes.c_double),
+                                  b.size, _dptr(e, ctypes.c_double), _dptr(cv, ctypes.c_double),
+                                  _dptr(m, ctypes.c_double), sp)
+    _check(rc)
+    return e, cv, m
 
 
 class Mlp:

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmuca.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("muca_kernels.hip", "muca_api.cpp", "mlp_kernels.hip", "mlp_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("muca_kernels.hip", "muca_api.cpp", "muca_static.hip", "mlp_kernels.hip",
+                                           "mlp_api.cpp")]
 HEADERS = [os.path.join(CSRC, "muca_device.h"), os.path.join(CSRC, "mlp_device.h"), os.path.join(INCLUDE, "muca.h")]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -792,6 +792,8 @@ void drop_graph(muca_ctx ctx) {
 
 }  // namespace
 
+void muca::set_context_free_error(const char *text) { g_init_error = text; }
+
 extern "C" {
 
 muca_status mucaWorkspaceSize(const muca_problem *problems, int32_t n, const muca_options *opts, size_t *bytes) {
@@ -1024,7 +1026,7 @@ muca_status mucaReweight(muca_ctx ctx, int32_t prob, const double *betas, int32_
     HIPCHECK(ctx, hipMemcpyAsync((void *)ctx->h_probdev[prob].lnW, p.lnW.data(), 8 * p.nbins,
                                  hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->d_betas, betas, 8 * n_betas, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHECK(ctx, launch_reweight(ctx->d_probs, prob, ctx->d_betas, n_betas, ctx->d_rw_out, ctx->stream));
+    HIPCHECK(ctx, launch_reweight(ctx->h_probdev[prob], ctx->d_betas, n_betas, ctx->d_rw_out, ctx->stream));
     std::vector<double> res(3 * (size_t)n_betas);
     HIPCHECK(ctx, hipMemcpyAsync(res.data(), ctx->d_rw_out, 8 * res.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));

@@ -81,8 +81,12 @@ hipError_t launch_advance(uint32_t *sweep_ctr, uint32_t n, hipStream_t stream);
 hipError_t launch_merge(const ProbDev *probs, const MergeItem *items, int n_items, int production,
                         int clear, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t value, size_t n, hipStream_t stream);
-hipError_t launch_reweight(const ProbDev *probs, int prob, const double *betas, int n_betas,
+// Eq. (2) over the bins of p (reads p.model, p.N, p.nbins, p.H, p.S, p.lnW).
+hipError_t launch_reweight(const ProbDev &p, const double *betas, int n_betas,
                            double *out /* [3][n_betas] */, hipStream_t stream);
 hipError_t launch_copy_bytes(void *dst, const void *src, size_t n, hipStream_t stream);
+
+// Error text of the calls that take no context (mucaLastError(NULL)).
+void set_context_free_error(const char *text);
 
 }  // namespace muca

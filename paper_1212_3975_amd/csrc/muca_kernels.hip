@@ -1558,10 +1558,8 @@ __device__ __forceinline__ double wave_max_d(double v) {
 // Eq. (2) over energy bins, one workgroup per beta: a bin with n_k
 // measurements taken under weight W(E_k) contributes n_k exp(-beta E_k) / W(E_k).
 // Outputs <E>/N, beta^2 var(E)/N and <|M|>/N into out[0..2][j].
-__global__ void __launch_bounds__(256) reweight_kernel(const ProbDev *probs, int prob, const double *betas,
-                                                        int n_betas, double *out) {
+__global__ void __launch_bounds__(256) reweight_kernel(ProbDev p, const double *betas, int n_betas, double *out) {
     __shared__ double red[4][4];
-    const ProbDev p = probs[prob];
     const int j = blockIdx.x;
     if (j >= n_betas) return;
     const double beta = betas[j];
@@ -1683,9 +1681,8 @@ hipError_t launch_copy_bytes(void *dst, const void *src, size_t n, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_reweight(const ProbDev *probs, int prob, const double *betas, int n_betas, double *out,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(reweight_kernel, dim3(n_betas), dim3(256), 0, s, probs, prob, betas, n_betas, out);
+hipError_t launch_reweight(const ProbDev &p, const double *betas, int n_betas, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(reweight_kernel, dim3(n_betas), dim3(256), 0, s, p, betas, n_betas, out);
     return hipGetLastError();
 }
 

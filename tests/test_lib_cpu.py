@@ -105,3 +105,36 @@ def test_mlp_workspace_size_and_create_validation_without_gpu_calls():
     assert L.mucaMlpCreate(ctypes.byref(m), 1000, 1, None, sizes[1000], None) != 0
     assert L.mucaMlpCreate(ctypes.byref(m), 1000, 1, ctypes.c_void_p(256 + 16), sizes[1000], None) != 0
     assert "aligned" in L.mucaMlpLastError(None).decode()
+
+
+def test_static_reweighting_validates_before_touching_a_gpu():
+    """mucaReweightStatic refuses bad arguments and sizes beyond its static
+    array on the host, before any HIP call (this runs without a GPU)."""
+    import numpy as np
+    L = 8
+    nb = 2 * L * L + 1
+    lnW, cnt, sab = np.zeros(nb), np.ones(nb, np.int64), np.zeros(nb, np.int64)
+    b = np.array([0.4])
+    cases = [
+        (dict(model=0, L=7), "even L"),                       # odd Ising L
+        (dict(model=0, L=258), "even L"),                     # beyond L = 256
+        (dict(model=1, L=257), "Potts needs L"),
+        (dict(model=2), "model must be"),
+        (dict(betas=np.zeros(4097)), "n_betas"),              # beyond 4096 beta
+        (dict(lnW=np.full(nb, np.nan)), "not finite"),
+        (dict(cnt=np.zeros(nb, np.int64)), "no production data"),
+        (dict(cnt=-np.ones(nb, np.int64)), "negative"),
+        (dict(sabs=None), "NULL"),                             # Ising without |M| sums
+        (dict(betas=np.array([np.inf])), "not finite"),
+    ]
+    for kw, msg in cases:
+        args = dict(model=0, L=L, lnW=lnW, cnt=cnt, sabs=sab, betas=b)
+        args.update(kw)
+        with pytest.raises(pm.MucaError, match=msg):
+            pm.reweight_static(**args)
+    # a size mismatch between the arrays is refused by the binding
+    with pytest.raises(ValueError):
+        pm.reweight_static(0, L, lnW, cnt[:-1], sab, b)
+    # n_bins must be 2N+1 for the stated L
+    with pytest.raises(pm.MucaError, match="2N"):
+        pm.reweight_static(0, 10, lnW, cnt, sab, b)
