@@ -11,6 +11,8 @@
 // terms of that chunk that the walker's updates can no longer change.  The
 // lattice (uint8 per site, chain fastest) and the acceptance table can each
 // live in LDS or in HBM; the host picks the placement per problem.
+#include <type_traits>
+
 #include "muca_device.h"
 
 namespace muca {
@@ -92,14 +94,23 @@ struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
     int off_rows;   // packed Ising walker only: the ring of unpacked rows
 };
-// The packed Ising walker (L = 64, more than 16 chains per workgroup): a lane's
-// lattice is 128 dwords of bits (stride 129), its row ring four rows of 16
-// byte dwords (stride 65), and random words come in chunks of half a row.
-constexpr int kPackedBitStride = 129;
-constexpr int kPackedRowStride = 65;
+// The packed Ising walker: L = 64 with more than 16 chains per workgroup
+// (32-bit table), and L = 96 and 128 with the compact table below.  A lane's
+// lattice is L*L/32 dwords of bits (odd stride), its row ring four rows of L/4
+// byte dwords (odd stride), and random words come in chunks of 32 sites.
 constexpr int kPackedChunkDwords = 8;
+__host__ __device__ constexpr int packed_bit_stride(int L) { return L * L / 32 + 1; }
+__host__ __device__ constexpr int packed_row_stride(int L) { return L + 1; }
+// Ising lattices whose 32-bit table does not fit in LDS beside their lattices:
+// the walker keeps a compact table there (one u16 per pair of neighbouring
+// rows, see run_ising_packed) and reads the full table in HBM only for the
+// rare draws the compact entry cannot decide.
+__host__ __device__ inline bool compact_ising(const ProbDev &p) {
+    return p.model == kIsing && (p.L == 96 || p.L == 128);
+}
+__host__ __device__ inline int compact_table_bytes(const ProbDev &p) { return 2 + 4 * (p.N + 1); }
 __host__ __device__ inline bool packed_ising(const ProbDev &p, const WorkItem &it) {
-    return p.model == kIsing && p.L == 64 && it.nchains > 16;
+    return p.model == kIsing && ((p.L == 64 && it.nchains > 16) || compact_ising(p));
 }
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves);
 __host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves);
@@ -115,12 +126,13 @@ __host__ __device__ constexpr int fast_lane_stride(int L) { return ((L * L / 4) 
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
     l.off_tab = 0;
-    const int tab = p.table_lds ? round_up(p.trows * p.tcols * 4, 16) : 0;
+    const bool compact = compact_ising(p) && fast_ising_ok(p, n_producer_waves);
+    const int tab = p.table_lds ? round_up(compact ? compact_table_bytes(p) : p.trows * p.tcols * 4, 16) : 0;
     l.off_spin = l.off_tab + tab;
     l.off_rows = 0;
     if (fast_ising_ok(p, n_producer_waves) && packed_ising(p, it)) {
-        l.off_rows = l.off_spin + round_up(it.nchains * kPackedBitStride * 4, 16);
-        l.off_ring = l.off_rows + round_up(it.nchains * kPackedRowStride * 4, 16);
+        l.off_rows = l.off_spin + round_up(it.nchains * packed_bit_stride(p.L) * 4, 16);
+        l.off_ring = l.off_rows + round_up(it.nchains * packed_row_stride(p.L) * 4, 16);
         l.total = l.off_ring + 2 * it.nchains * (kPackedChunkDwords + 1) * 16;
         return l;
     }
@@ -158,7 +170,7 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
 // unit of the walkers' int32 loop counters).
 int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     if (fast_ising_ok(p, n_producer_waves)) {
-        if (p.model == kIsing && packed_ising(p, it)) return 64 * 16 / kPackedChunkDwords;
+        if (p.model == kIsing && packed_ising(p, it)) return p.L * (p.L / 4) / kPackedChunkDwords;
         return p.L / fast_rows_per_chunk(p.L);
     }
     if (fast_potts_ok(p, n_producer_waves)) return p.L / potts_rows_per_chunk(p.L, potts_wide(it.nchains));
@@ -166,10 +178,10 @@ int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves)
 }
 
 // The fast Ising walker (and its multimagnetic variant) has compiled shapes
-// for these sizes and needs both
-// arrays in LDS and producer waves.
+// for these sizes (Ising also 96 and 128, packed with the compact table) and
+// needs both arrays in LDS and producer waves.
 __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_waves) {
-    const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32 || p.L == 48 || p.L == 64;
+    const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32 || p.L == 48 || p.L == 64 || compact_ising(p);
     return (p.model == kIsing || p.model == kIsingMag) && size_ok && p.spin_lds && p.table_lds &&
            n_producer_waves > 0;
 }
@@ -255,7 +267,7 @@ struct TabRef<false> {
 // "stored < T" means T == 0xffffffff or u < T.  Potts also stores the
 // proposal offset floor(r (q-1) / 2^32).
 template <int MODEL>
-__device__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint32_t ring, int t, int nchunks,
+__device__ __forceinline__ void produce_chunk(const ProbDev &p, const WorkItem &it, uint32_t ring, int t, int nchunks,
                               uint32_t sweep0, int ptid, int nprod_threads) {
     const int sw = t / nchunks;
     const int chunk = t - sw * nchunks;
@@ -607,7 +619,7 @@ __device__ __forceinline__ uint2 ising_pre(uint32_t cur, uint32_t prv, uint32_t 
 }
 
 template <int L, bool MAG>
-__device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+__device__ __forceinline__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
     // table row bytes: Ising rows k/2 of five words, multimagnetic rows m of ten
     constexpr uint32_t RB = MAG ? 40u : 20u;
@@ -824,19 +836,36 @@ __device__ void run_ising_fast(const ProbDev &p, const WorkItem &it, char *lds, 
 }
 
 
-// ------------------------------------------------------------------ packed Ising walker (L = 64)
+// ------------------------------------------------------------------ packed Ising walker
 //
 // At L = 64 a byte per spin is 4 KB per chain: with the 80 KB table only 16
 // chains fit in LDS, so a walker wave would run with a quarter of its lanes.
-// Here each lattice is kept as bits (bit x of dwords 2y, 2y+1 is site (x, y))
-// and the byte-wise walker above reads a ring of four unpacked rows per lane.
-// While row y is updated, the ring holds row y-1 (already updated), row y
-// (updated in place, a dword at a time) and row y+1 (old), and row y+2 is
-// unpacked into the fourth slot, one dword per updated dword.  The flips are
-// collected as one nibble per dword and xored into the packed row when the row
-// is done.  Rows wrap modulo L, so at row L-2 the already updated row 0 is
-// unpacked for the next sweep.  Random words come in chunks of half a row.
-// The site order, random words and tables are those of the byte walker.
+// Here each lattice is kept as bits (bit x of dwords y*L/32 .. y*L/32 + L/32-1
+// is site (x, y)) and the byte-wise walker above reads a ring of four unpacked
+// rows per lane.  While row y is updated, the ring holds row y-1 (already
+// updated), row y (updated in place, a dword at a time) and row y+1 (old), and
+// row y+2 is unpacked into the fourth slot, one dword per updated dword.  The
+// flips are collected as one nibble per dword and xored into the packed row
+// at the end of each chunk of 32 sites (one bit dword).  Rows wrap modulo L,
+// so at row L-2 the already updated row 0 is unpacked for the next sweep.
+// Random words come in chunks of 32 sites.  The site order, random words and
+// acceptance rule are those of the byte walker.
+//
+// Compact table (L = 96, 128, where the 32-bit table would not leave room for
+// the lattices).  For rows kk and kk+j (j = 1, 2) the two thresholds are
+// T(kk -> kk+j) and T(kk+j -> kk), computed from lnW[kk+j] - lnW[kk] and its
+// exact negative, so at least one of them is the "always" value.  One u16
+// holds the other: bit 14 set when the move down (kk+j -> kk) is the one that
+// can be rejected, bits 0..13 the top 14 bits of its threshold.  The entry of
+// pair (kk, kk+j) sits at byte 4 kk + 2 j (after a 2-byte pad), so a move by
+// d rows from row kk reads byte 4 kk + 2 d whatever the sign of d.  The walker
+// decodes the entry per candidate by xoring bit 14 for a move down (making an
+// up-rejectable entry >= 0x4000, i.e. always) and bit 15 for a move that keeps
+// k (always), and compares it with the top 14 bits a of the clamped draw:
+// a < t accepts, a > t rejects, and a == t (about one site in 2^14) cannot be
+// decided from the prefix.  A dword with such a site is redone exactly: the
+// full threshold comes from the 32-bit table in HBM and the draw is drawn
+// again from the generator.  Every decision therefore equals the 32-bit rule.
 
 template <int V>
 struct IntConst {
@@ -848,12 +877,158 @@ __device__ __forceinline__ uint32_t spread_nibble(uint32_t n) {
     return __umul24(n, 0x00204081u) & 0x01010101u;
 }
 
-__device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
-                                   uint32_t sweep0, const LdsPlan &plan) {
-    constexpr int L = 64, W = 16, NB = 128;            // dwords per row (bytes), bit dwords per lattice
-    constexpr int CDW = kPackedChunkDwords, NCH = L * W / CDW;   // chunks per sweep
-    constexpr int PB = kPackedBitStride, PR = kPackedRowStride;
-    constexpr uint32_t RB = 20u;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+__device__ __forceinline__ uint32_t lds_ld16(uint32_t a) { return *(const lds_u16 *)(size_t)a; }
+
+// Compact entry of the pair (kk, kk+j) from the two 32-bit thresholds.
+__device__ __forceinline__ uint16_t compact_entry(uint32_t t_up, uint32_t t_down) {
+    if (t_up != 0xFFFFFFFFu) return (uint16_t)(t_up >> 18);
+    if (t_down != 0xFFFFFFFFu) return (uint16_t)(0x4000u | (t_down >> 18));
+    return 0x3FFFu;   // both always: an up move compares with the largest prefix, a tie decides exactly
+}
+
+// Bulk of one dword for the compact table: besides the old spins, the column
+// codes (2 d + 4, d = 2 - D the row move), the row steps (4 d bytes) and the
+// decode codes (byte 1 of the xor: 0x40 for a move down, 0x80 for d = 0) of
+// both candidates.
+struct CompactBulk {
+    uint32_t cur, a0, a1, e0, e1, z0, z1;
+};
+
+__device__ __forceinline__ void compact_cols(const BulkDiff &d, CompactBulk &b) {
+    b.cur = d.cur;
+    b.a0 = __builtin_amdgcn_perm(0u, 0x02040608u, d.d0);   // D = 0..4 -> 8, 6, 4, 2, 0
+    b.a1 = __builtin_amdgcn_perm(0u, 0x02040608u, d.d1);
+}
+__device__ __forceinline__ void compact_steps(const BulkDiff &d, CompactBulk &b) {
+    b.e0 = __builtin_amdgcn_perm(0xF8u, 0xFC000408u, d.d0);   // 8, 4, 0, -4, -8
+    b.e1 = __builtin_amdgcn_perm(0xF8u, 0xFC000408u, d.d1);
+    b.z0 = __builtin_amdgcn_perm(0x40u, 0x40800000u, d.d0);   // 0, 0, 0x80, 0x40, 0x40
+    b.z1 = __builtin_amdgcn_perm(0x40u, 0x40800000u, d.d1);
+}
+__device__ __forceinline__ int32_t row_step(const CompactBulk &b, bool left_flipped, int j) {
+    return left_flipped ? sbyte(b.e1, j) : sbyte(b.e0, j);
+}
+
+// Walker state and flip record of an exactly recomputed dword.
+struct RedoResult {
+    FastState s;
+    uint32_t f;
+};
+
+// Exact recomputation of one dword of the compact walker (rare: some site of
+// the dword drew a prefix equal to its entry's).  From the state at the
+// dword's start (rows R, C and the previous site's outcome acc), each site is
+// decided from its decoded entry where the prefix decides, else from the full
+// threshold T32[kk][d + 2] in HBM and the site's draw regenerated from the
+// generator (block blk of the sweep, word j).  Returns the state after the
+// dword, with the next dword's first entries read for both outcomes (column
+// codes na0, na1), and the flip record (bit j for an accepted site j).  Kept
+// out of line so that the walker's state stays in registers on the fast path.
+__device__ __noinline__ RedoResult redo_compact_dword(uint32_t R, uint32_t C, uint32_t acc_in, uint32_t ca0,
+                                                      uint32_t ca1, uint32_t ce0, uint32_t ce1, uint32_t cz0,
+                                                      uint32_t cz1, uint32_t na0, uint32_t na1, uint32_t u0,
+                                                      uint32_t u1, uint32_t u2, uint32_t u3, uint32_t tab0,
+                                                      const uint32_t *table, uint32_t blk, uint32_t sweep,
+                                                      uint32_t chain, uint32_t seed_lo, uint32_t seed_hi) {
+    const g_u32 *T = (const g_u32 *)table;
+    bool acc = acc_in != 0;
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t Rj = acc ? C : R;
+        const int32_t step = acc ? sbyte(ce1, j) : sbyte(ce0, j);
+        const uint32_t code = acc ? ubyte(ca1, j) : ubyte(ca0, j);
+        const uint32_t z = acc ? ubyte(cz1, j) : ubyte(cz0, j);
+        const uint32_t t = lds_ld16(Rj + code) ^ (z << 8);
+        const uint32_t a = (j == 0) ? u0 : (j == 1) ? u1 : (j == 2) ? u2 : u3;
+        bool ok;
+        if (a != t) {
+            ok = a < t;
+        } else {
+            // full threshold: row kk = (Rj + 4 - tab0) / 4, column d + 2 with d = step / 4
+            const int kk = (int)((Rj + 4u - tab0) >> 2);
+            const uint32_t Tf = T[kk * 5 + 2 + (step >> 2)];
+            const uint4 b = philox4x32_10(blk, sweep, chain, 0u, seed_lo, seed_hi);
+            const uint32_t uu = (j == 0) ? b.x : (j == 1) ? b.y : (j == 2) ? b.z : b.w;
+            ok = min(uu, 0xFFFFFFFEu) < Tf;
+        }
+        R = Rj;
+        C = Rj + (uint32_t)step;
+        acc = ok;
+        if (ok) f |= 1u << j;
+    }
+    RedoResult r;
+    r.s = FastState{R, C, lds_ld16(R + na0), lds_ld16(C + na1), acc};
+    r.f = f;
+    return r;
+}
+
+// The four sites of one dword against the compact table; as walk_dword, plus
+// the decode of each candidate's entry and the detection of undecidable
+// draws.  If any site of the dword drew a == t, the whole dword is recomputed
+// exactly from the state at its start (redo_compact_dword; ex holds the
+// table, the Philox block of the dword and the generator's key).
+struct CompactExact {
+    uint32_t tab0;
+    const uint32_t *table;
+    uint32_t blk, sweep, chain, seed_lo, seed_hi;
+};
+
+template <uint32_t FLIP, int STRIDE, class Work>
+__device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const CompactBulk &b, const CompactBulk &nb,
+                                                       const uint4 &u, Work &&work, const CompactExact &ex) {
+    const FastState s0 = s;
+    uint32_t f = 0;
+    bool tie = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t Rj = s.acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)row_step(b, s.acc, j);
+        const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
+        const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
+        const uint32_t nA = lds_ld16(Rj + a0);
+        const uint32_t nB = lds_ld16(Cj + a1);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t tA = s.tA ^ (ubyte(b.z0, j) << 8);
+        const uint32_t tB = s.tB ^ (ubyte(b.z1, j) << 8);
+        const uint32_t tj = s.acc ? tB : tA;
+        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+        s.acc = uj < tj;
+        tie |= uj == tj;
+        s.R = Rj;
+        s.C = Cj;
+        s.tA = nA;
+        s.tB = nB;
+        __builtin_amdgcn_sched_barrier(0);
+        work(j);
+        __builtin_amdgcn_sched_barrier(0);
+        f |= s.acc ? (FLIP << (STRIDE * j)) : 0u;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (tie) {
+        static_assert(FLIP == 1u && STRIDE == 1, "the exact redo writes a nibble");
+        const RedoResult r = redo_compact_dword(s0.R, s0.C, s0.acc ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1,
+                                                ubyte(nb.a0, 0), ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0,
+                                                ex.table, ex.blk, ex.sweep, ex.chain, ex.seed_lo, ex.seed_hi);
+        s = r.s;
+        f = r.f;
+    }
+    return f;
+}
+
+template <int L, bool COMPACT>
+__device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                                 uint32_t sweep0, const LdsPlan &plan) {
+    constexpr int W = L / 4;                    // byte dwords per row
+    constexpr int BPR = L / 32;                 // bit dwords per row = chunks per row
+    constexpr int NB = L * BPR;                 // bit dwords per lattice
+    constexpr int CDW = kPackedChunkDwords;     // byte dwords per chunk (one bit dword)
+    constexpr int NCH = L * BPR;                // chunks per sweep
+    constexpr int PB = packed_bit_stride(L), PR = packed_row_stride(L);
+    constexpr uint32_t RB = COMPACT ? 4u : 20u;   // table row bytes
+    static_assert(W == CDW * BPR, "packed walker shape");
+    using Bulk = typename std::conditional<COMPACT, CompactBulk, FastBulk>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nthreads = blockDim.x;
     const int nch = it.nchains;
@@ -864,7 +1039,24 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
     const uint32_t rows0 = lbase + (uint32_t)plan.off_rows;
     const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
     const uint32_t ringbuf = (uint32_t)nch * (CDW + 1) * 16u;
+    // compact rows: entry (kk, j) sits at tab0 + 4 kk + 2 j (tab0 holds the
+    // pad); R = tab0 + 4 kk - 4, so that R + (2 d + 4) is the entry a move by
+    // d rows reads, for d = -2..2 (d = 0 reads a valid entry it ignores)
+    auto row_of = [&](int kk) -> uint32_t { return COMPACT ? tab0 + 4u * (uint32_t)kk - 4u : tab0 + RB * (uint32_t)kk; };
+    auto kk_of = [&](uint32_t R) -> int { return COMPACT ? (int)((R + 4u - tab0) >> 2) : (int)((R - tab0) / RB); };
 
+    if constexpr (COMPACT) {
+        // the pair table, from the 32-bit table in HBM (rows kk, columns dk/2 + 2)
+        const g_u32 *T = (const g_u32 *)p.table;
+        const int rows = p.N + 1;
+        if (tid == 0) *(lds_u16 *)(size_t)tab0 = 0;
+        for (int e = tid; e < 2 * rows; e += nthreads) {
+            const int kk = e >> 1, j = (e & 1) + 1;
+            uint16_t v = 0;
+            if (kk + j < rows) v = compact_entry(T[kk * 5 + 2 + j], T[(kk + j) * 5 + 2 - j]);
+            *(lds_u16 *)(size_t)(tab0 + 2u + 2u * (uint32_t)e) = v;
+        }
+    }
     // stage the lattice as bits: dword d of lane c holds sites 32d..32d+31
     for (int j = tid; j < NB * nch; j += nthreads) {
         const int d = j / nch, c = j - d * nch;
@@ -878,15 +1070,26 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
     const uint32_t bl = bits0 + (uint32_t)(lane * PB) * 4u;   // this lane's bits
     const uint32_t rl = rows0 + (uint32_t)(lane * PR) * 4u;   // this lane's row ring
     const uint32_t rb = ring0 + (uint32_t)(lane * (CDW + 1)) * 16u;
+    const uint32_t chain = (uint32_t)(it.chain0 + lane);
     auto slot = [&](int y) -> uint32_t { return rl + (uint32_t)((y & 3) * W) * 4u; };
     // byte dword w of row y, unpacked from the bits
     auto unpacked = [&](int y, int w) -> uint32_t {
-        const uint32_t word = lds_ld(bl + (uint32_t)(2 * y + (w >> 3)) * 4u);
+        const uint32_t word = lds_ld(bl + (uint32_t)(BPR * y + (w >> 3)) * 4u);
         return spread_nibble(__builtin_amdgcn_ubfe(word, 4u * (uint32_t)(w & 7), 4u));
+    };
+    auto read_t = [&](uint32_t a) -> uint32_t { return COMPACT ? lds_ld16(a) : lds_ld(a); };
+    auto make_bulk = [&](const BulkDiff &d, Bulk &b) {
+        if constexpr (COMPACT) {
+            compact_cols(d, b);
+            compact_steps(d, b);
+        } else {
+            bulk_cols<false>(d, b);
+            bulk_steps<false>(d, b);
+        }
     };
 
     FastState st{0, 0, 0, 0, false};
-    FastBulk nb{0, 0, 0, 0, 0};
+    Bulk nb{};
     if (active) {
         // ring: rows L-1, 0, 1 (row 2 is unpacked while row 0 is updated)
         for (int w = 0; w < W; ++w) {
@@ -895,16 +1098,18 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
             lds_st(slot(1) + 4u * w, unpacked(1, w));
         }
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
-        st.R = tab0 + RB * (uint32_t)(k >> 1);
+        st.R = row_of(k >> 1);
         st.C = st.R;
         const uint32_t r0 = slot(0);
-        nb = fast_bulk<true>(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(slot(L - 1)),
-                             lds_ld(slot(1)));
-        st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
+        make_bulk(bulk_diff<true>(bulk_sums(lds_ld(r0), lds_ld(r0 + 4 * (W - 1)), lds_ld(r0 + 4), lds_ld(slot(L - 1)),
+                                            lds_ld(slot(1)))),
+                  nb);
+        st.tA = read_t(st.R + ubyte(nb.a0, 0));
         st.tB = st.tA;
     }
 
-    // producers: chunk t covers dwords (t mod NCH) * CDW .. + CDW - 1 of sweep t / NCH
+    // producers: chunk t covers dwords (t mod NCH) * CDW .. + CDW - 1 of sweep t / NCH;
+    // the compact walker receives the top 14 bits of each clamped draw
     auto produce = [&](int t) {
         const int sw = t / NCH;
         const uint32_t sweep = sweep0 + (uint32_t)sw;
@@ -915,32 +1120,35 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
             const int c = w / CDW, q = w - c * CDW;
             const uint4 b = philox4x32_10((uint32_t)(blk0 + q), sweep, (uint32_t)(it.chain0 + c), 0u, p.seed_lo,
                                           p.seed_hi);
-            lds_st4(buf + (uint32_t)(c * (CDW + 1) + q) * 16u,
-                    make_uint4(min(b.x, 0xFFFFFFFEu), min(b.y, 0xFFFFFFFEu), min(b.z, 0xFFFFFFFEu),
-                               min(b.w, 0xFFFFFFFEu)));
+            uint4 o = make_uint4(min(b.x, 0xFFFFFFFEu), min(b.y, 0xFFFFFFFEu), min(b.z, 0xFFFFFFFEu),
+                                 min(b.w, 0xFFFFFFFEu));
+            if (COMPACT) o = make_uint4(o.x >> 18, o.y >> 18, o.z >> 18, o.w >> 18);
+            lds_st4(buf + (uint32_t)(c * (CDW + 1) + q) * 16u, o);
         }
     };
 
-    const int total_chunks = NCH * l.n_sweeps;   // even: two halves per row
+    const int total_chunks = NCH * l.n_sweeps;
     if (wave > 0) produce(0);
     __syncthreads();
     uint4 u_next = make_uint4(0, 0, 0, 0);
-    uint32_t fl0 = 0, fl1 = 0;   // flips of the current row: sites 0..31, 32..63
-    // One half row; H is a compile-time constant so that every dword index,
-    // LDS offset and flip word below is fixed at compile time.
-    auto walk_half = [&](auto HC, int t) {
+    // One chunk of 32 sites (bit dword H of row y); H is a compile-time
+    // constant so that every dword index, LDS offset and flip word below is
+    // fixed at compile time.
+    auto walk_chunk = [&](auto HC, int t) {
         constexpr int H = decltype(HC)::value;
-        const int y = (t % NCH) >> 1;
+        const int sw = t / NCH;
+        const int y = (t - sw * NCH) / BPR;
+        const uint32_t sweep = sweep0 + (uint32_t)sw;
         const uint32_t ub = rb + (uint32_t)(t & 1) * ringbuf;
         const uint32_t vcur = slot(y), vnc = slot(y + 1), vnd = slot(y + 2), vup = slot(y + 3);
         const int y2 = (y + 2 == L) ? 0 : (y + 2 == L + 1) ? 1 : y + 2;   // row unpacked into vnd
-        const uint32_t bits_y2 = bl + (uint32_t)(2 * y2 + H) * 4u;        // its half of row y2
-        const uint32_t word_y2 = lds_ld(bits_y2);
+        const uint32_t word_y2 = lds_ld(bl + (uint32_t)(BPR * y2 + H) * 4u);   // its chunk H
         uint32_t nxt_cache = lds_ld(vcur + 4 * (8 * H + 1));
+        uint32_t fl = 0;   // flips of this chunk, one bit per site
 #pragma unroll
         for (int q = 0; q < CDW; ++q) {
             const int w = 8 * H + q;
-            const FastBulk b = nb;
+            const Bulk b = nb;
             const uint4 u = (q == 0) ? lds_ld4(ub) : u_next;
             // the next dword's bulk (and one dword of row y+2 into the ring),
             // in pieces between this dword's sites
@@ -968,59 +1176,65 @@ __device__ void run_ising_packed64(const ProbDev &p, const WorkItem &it, char *l
                     if (w + 1 < W) nxt_cache = q2;
                 } else if (j == 2) {
                     nd = (w + 1 < W) ? bulk_diff<false>(ns) : bulk_diff<true>(ns);
-                    bulk_cols<false>(nd, nb);
+                    if constexpr (COMPACT) compact_cols(nd, nb);
+                    else bulk_cols<false>(nd, nb);
                 } else {
-                    bulk_steps<false>(nd, nb);
+                    if constexpr (COMPACT) compact_steps(nd, nb);
+                    else bulk_steps<false>(nd, nb);
                     // row y+2 into the ring (the slot of row y-2, no longer read)
                     lds_st(vnd + 4u * w, spread_nibble(__builtin_amdgcn_ubfe(word_y2, 4u * (uint32_t)q, 4u)));
                 }
             };
-            const uint32_t nib = walk_dword<FastBulk, 1u, 1>(st, b, nb, u, work);
+            uint32_t nib;
+            if constexpr (COMPACT) {
+                const CompactExact ex{tab0, p.table, (uint32_t)(y * W + w), sweep, chain, p.seed_lo, p.seed_hi};
+                nib = walk_dword_compact<1u, 1>(st, b, nb, u, work, ex);
+            } else {
+                nib = walk_dword<FastBulk, 1u, 1>(st, b, nb, u, work);
+            }
             lds_st(vcur + 4 * w, b.cur ^ spread_nibble(nib));
-            if (H == 0) fl0 |= nib << (4 * q);
-            else fl1 |= nib << (4 * q);
+            fl |= nib << (4 * q);
         }
-        if (H == 1) {
-            // row y done: fold its flips into the bits
-            const uint32_t a0 = bl + (uint32_t)(2 * y) * 4u;
-            lds_st(a0, lds_ld(a0) ^ fl0);
-            lds_st(a0 + 4u, lds_ld(a0 + 4u) ^ fl1);
-            fl0 = 0;
-            fl1 = 0;
-            if (y == L - 1 && l.record != kRecNone) {
-                const uint32_t Rk = st.acc ? st.C : st.R;
-                const int k = 2 * (int)((Rk - tab0) / RB);
-                const int64_t cidx = (int64_t)k * p.C + it.chain0 + lane;
-                g_i32 *hh = (g_i32 *)p.hist;
-                hh[cidx] += 1;
-                if (l.record == kRecProd) {
-                    int ones = 0;
-                    for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
-                    const int m = 2 * ones - L * L;
-                    g_i64 *s = (g_i64 *)p.sabs;
-                    s[cidx] += (int64_t)(m < 0 ? -m : m);
-                }
+        // chunk done: fold its flips into the bits of row y
+        const uint32_t a0 = bl + (uint32_t)(BPR * y + H) * 4u;
+        lds_st(a0, lds_ld(a0) ^ fl);
+        if (H == BPR - 1 && y == L - 1 && l.record != kRecNone) {
+            const uint32_t Rk = st.acc ? st.C : st.R;
+            const int k = 2 * kk_of(Rk);
+            const int64_t cidx = (int64_t)k * p.C + it.chain0 + lane;
+            g_i32 *hh = (g_i32 *)p.hist;
+            hh[cidx] += 1;
+            if (l.record == kRecProd) {
+                int ones = 0;
+                for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
+                const int m = 2 * ones - L * L;
+                g_i64 *s = (g_i64 *)p.sabs;
+                s[cidx] += (int64_t)(m < 0 ? -m : m);
             }
         }
     };
-    for (int t = 0; t < total_chunks; t += 2) {
+    // chunk H of a row, then the barrier that hands the next chunk's random
+    // words over
+    auto chunk_pass = [&](auto HC, int t) {
+        constexpr int H = decltype(HC)::value;
         if (wave == 0) {
-            if (active) walk_half(IntConst<0>{}, t);
-        } else {
-            produce(t + 1);
+            if (active) walk_chunk(IntConst<H>{}, t + H);
+        } else if (t + H + 1 < total_chunks) {
+            produce(t + H + 1);
         }
         __syncthreads();
-        if (wave == 0) {
-            if (active) walk_half(IntConst<1>{}, t + 1);
-        } else if (t + 2 < total_chunks) {
-            produce(t + 2);
-        }
-        __syncthreads();
+    };
+    static_assert(BPR >= 2 && BPR <= 4, "packed walker rows of 2 to 4 chunks");
+    for (int t = 0; t < total_chunks; t += BPR) {
+        chunk_pass(IntConst<0>{}, t);
+        chunk_pass(IntConst<1>{}, t);
+        if constexpr (BPR > 2) chunk_pass(IntConst<2>{}, t);
+        if constexpr (BPR > 3) chunk_pass(IntConst<3>{}, t);
     }
 
     if (active) {
         const uint32_t Rk = st.acc ? st.C : st.R;
-        ((g_i32 *)p.k)[it.chain0 + lane] = 2 * (int)((Rk - tab0) / RB);
+        ((g_i32 *)p.k)[it.chain0 + lane] = 2 * kk_of(Rk);
         int ones = 0;
         for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
         ((g_i32 *)p.m)[it.chain0 + lane] = 2 * ones - L * L;
@@ -1039,8 +1253,12 @@ template <bool MAG>
 __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                       const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
     if (!MAG && packed_ising(p, it)) {
-        run_ising_packed64(p, it, lds, l, sweep0, plan);
-        return true;
+        switch (p.L) {
+        case 64: run_ising_packed<64, false>(p, it, lds, l, sweep0, plan); return true;
+        case 96: run_ising_packed<96, true>(p, it, lds, l, sweep0, plan); return true;
+        case 128: run_ising_packed<128, true>(p, it, lds, l, sweep0, plan); return true;
+        default: return false;
+        }
     }
     switch (p.L) {
     case 16: run_ising_fast<16, MAG>(p, it, lds, l, sweep0, plan); return true;
@@ -1154,7 +1372,7 @@ __device__ __forceinline__ uint32_t potts_left(uint32_t b1, uint32_t T, uint32_t
 }
 
 template <int L, bool WIDE>
-__device__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+__device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
     constexpr int W = L / 4;
     constexpr int NW = L * L / 4;
@@ -1369,8 +1587,11 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     TabRef<TAB_LDS> tab;
     if constexpr (TAB_LDS) {
         tab.base = lbase + (uint32_t)plan.off_tab;
-        const int n = p.trows * p.tcols;
-        for (int j = tid; j < n; j += nthreads) lds_st(tab.base + 4u * (uint32_t)j, ((const g_u32 *)p.table)[j]);
+        // the compact-table walker builds its own (smaller) table in LDS
+        if (!(compact_ising(p) && fast_ising_ok(p, l.n_producer_waves))) {
+            const int n = p.trows * p.tcols;
+            for (int j = tid; j < n; j += nthreads) lds_st(tab.base + 4u * (uint32_t)j, ((const g_u32 *)p.table)[j]);
+        }
     } else {
         tab.base = (const g_u32 *)p.table;
     }
