@@ -122,12 +122,26 @@ __host__ __device__ constexpr bool potts_wide(int nchains) { return nchains > 32
 __host__ __device__ constexpr int potts_rows_per_chunk(int L, bool wide) {
     return wide ? (32 + L - 1) / L : (64 + L - 1) / L;
 }
+// 8-state Potts at L = 48: the fast Potts walker with a compact table (one u16
+// per pair of rows (k, k+j), j = 1..4, see run_potts_fast), in chunks of one
+// row whatever the chain count.
+__host__ __device__ inline bool compact_potts(const ProbDev &p) { return p.model == kPotts && p.q == 8 && p.L == 48; }
+constexpr int kPottsGuardBytes = 256;   // free LDS before the compact Potts table
+__host__ __device__ inline int compact_potts_table_bytes(const ProbDev &p) { return 2 + 8 * (2 * p.N + 1); }
+__host__ __device__ inline bool potts_wide_item(const ProbDev &p, const WorkItem &it) {
+    return potts_wide(it.nchains) || compact_potts(p);
+}
 __host__ __device__ constexpr int fast_lane_stride(int L) { return ((L * L / 4) % 2) ? L * L / 4 : L * L / 4 + 1; }
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
     l.off_tab = 0;
-    const bool compact = compact_ising(p) && fast_ising_ok(p, n_producer_waves);
-    const int tab = p.table_lds ? round_up(compact ? compact_table_bytes(p) : p.trows * p.tcols * 4, 16) : 0;
+    const bool compact_i = compact_ising(p) && fast_ising_ok(p, n_producer_waves);
+    const bool compact_p = compact_potts(p) && fast_potts_ok(p, n_producer_waves);
+    const int tab = !p.table_lds ? 0
+                    : round_up(compact_i ? compact_table_bytes(p)
+                                         : compact_p ? kPottsGuardBytes + compact_potts_table_bytes(p)
+                                                     : p.trows * p.tcols * 4,
+                               16);
     l.off_spin = l.off_tab + tab;
     l.off_rows = 0;
     if (fast_ising_ok(p, n_producer_waves) && packed_ising(p, it)) {
@@ -149,7 +163,7 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
         // lane-major lattice; ring of three buffers: [3][lane][chunk dwords + 1] uint4 words
         // followed by [3][lane][chunk dwords + 1] uint4 lattice terms
         const int W = p.L / 4;
-        const int cdw = potts_rows_per_chunk(p.L, potts_wide(it.nchains)) * W;
+        const int cdw = potts_rows_per_chunk(p.L, potts_wide_item(p, it)) * W;
         l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
         l.total = l.off_ring + 3 * it.nchains * (cdw + 1) * 32;
         return l;
@@ -173,7 +187,7 @@ int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves)
         if (p.model == kIsing && packed_ising(p, it)) return p.L * (p.L / 4) / kPackedChunkDwords;
         return p.L / fast_rows_per_chunk(p.L);
     }
-    if (fast_potts_ok(p, n_producer_waves)) return p.L / potts_rows_per_chunk(p.L, potts_wide(it.nchains));
+    if (fast_potts_ok(p, n_producer_waves)) return p.L / potts_rows_per_chunk(p.L, potts_wide_item(p, it));
     return (p.N + kChunkSites - 1) / kChunkSites;
 }
 
@@ -185,9 +199,10 @@ __host__ __device__ inline bool fast_ising_ok(const ProbDev &p, int n_producer_w
     return (p.model == kIsing || p.model == kIsingMag) && size_ok && p.spin_lds && p.table_lds &&
            n_producer_waves > 0;
 }
-// The fast Potts walker: q = 8, compiled sizes, both arrays in LDS, producers.
+// The fast Potts walker: q = 8, compiled sizes (48 with the compact table),
+// both arrays in LDS, producers.
 __host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_waves) {
-    const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32;
+    const bool size_ok = p.L == 16 || p.L == 24 || p.L == 32 || compact_potts(p);
     return p.model == kPotts && p.q == 8 && size_ok && p.spin_lds && p.table_lds && n_producer_waves > 0;
 }
 
@@ -975,9 +990,16 @@ struct CompactExact {
     uint32_t blk, sweep, chain, seed_lo, seed_hi;
 };
 
-template <uint32_t FLIP, int STRIDE, class Work>
-__device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const CompactBulk &b, const CompactBulk &nb,
-                                                       const uint4 &u, Work &&work, const CompactExact &ex) {
+__device__ __forceinline__ RedoResult compact_redo(const FastState &s0, const CompactBulk &b, const CompactBulk &nb,
+                                                   const uint4 &u, const CompactExact &ex) {
+    return redo_compact_dword(s0.R, s0.C, s0.acc ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1, ubyte(nb.a0, 0),
+                              ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain,
+                              ex.seed_lo, ex.seed_hi);
+}
+
+template <class Bulk, uint32_t FLIP, int STRIDE, class Work>
+__device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const Bulk &b, const Bulk &nb, const uint4 &u,
+                                                       Work &&work, const CompactExact &ex) {
     const FastState s0 = s;
     uint32_t f = 0;
     bool tie = false;
@@ -1007,10 +1029,9 @@ __device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const Compa
         __builtin_amdgcn_sched_barrier(0);
     }
     if (tie) {
-        static_assert(FLIP == 1u && STRIDE == 1, "the exact redo writes a nibble");
-        const RedoResult r = redo_compact_dword(s0.R, s0.C, s0.acc ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1,
-                                                ubyte(nb.a0, 0), ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0,
-                                                ex.table, ex.blk, ex.sweep, ex.chain, ex.seed_lo, ex.seed_hi);
+        // the exact redo writes the flip record in the walker's format
+        // (FLIP << STRIDE j for an accepted site j)
+        const RedoResult r = compact_redo(s0, b, nb, u, ex);
         s = r.s;
         f = r.f;
     }
@@ -1188,7 +1209,7 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
             uint32_t nib;
             if constexpr (COMPACT) {
                 const CompactExact ex{tab0, p.table, (uint32_t)(y * W + w), sweep, chain, p.seed_lo, p.seed_hi};
-                nib = walk_dword_compact<1u, 1>(st, b, nb, u, work, ex);
+                nib = walk_dword_compact<CompactBulk, 1u, 1>(st, b, nb, u, work, ex);
             } else {
                 nib = walk_dword<FastBulk, 1u, 1>(st, b, nb, u, work);
             }
@@ -1371,7 +1392,92 @@ __device__ __forceinline__ uint32_t potts_left(uint32_t b1, uint32_t T, uint32_t
     return b1 + __builtin_amdgcn_ubfe(T, sp_prv >> 23, 2u);
 }
 
-template <int L, bool WIDE>
+// Compact table of the Potts walker (L = 48): as for the Ising walker, the
+// pair of rows (k, k+j), j = 1..4, has one rejectable direction, stored in a
+// u16 (bit 14 set when it is the move down; bits 0..13 the top 14 bits of its
+// threshold).  Entry (k, j) sits at byte 8 k + 2 j after a 2-byte pad, so a
+// move by d reads 8 k + 2 d for d > 0 and 8 k + 6 d for d < 0.  With the row
+// register R = tab0 + 8 k - 247 the column codes 247 + (2 d or 6 d) are
+// 223..255, one v_perm lookup on dk + 4 (the selector 8 of dk = +4 copies bit
+// 7 of byte 1 of the low source, which is set: 0xff).  The decode code (byte
+// 1 of the xor) is 0x40 for a move down and 0x80 for dk = 0.  The walker
+// keeps 256 bytes free before the table, so that every code addresses LDS
+// inside the workgroup's allocation whatever the row.
+constexpr uint32_t kPottsCompactBias = 247;
+constexpr uint32_t kPottsCompactGuard = kPottsGuardBytes;
+
+struct CompactPottsBulk {
+    uint32_t cur, sp;   // old states, proposals
+    uint32_t a0, a1;    // column codes of candidates 0 / 1
+    uint32_t k0, k1;    // dk bytes (int8)
+    uint32_t z0, z1;    // decode codes
+};
+
+__device__ __forceinline__ void potts_maps_c(uint2 bd, CompactPottsBulk &b) {
+    const uint32_t i0 = bd.x - 0x7C7C7C7Cu, i1 = bd.y - 0x7C7C7C7Cu;   // dk + 4 per byte
+    b.a0 = __builtin_amdgcn_perm(0xFDFBF9F7u, 0xF1EBE5DFu, i0);          // 223 229 235 241 247 249 251 253 255
+    b.a1 = __builtin_amdgcn_perm(0xFDFBF9F7u, 0xF1EBE5DFu, i1);
+    b.z0 = __builtin_amdgcn_perm(0x00000080u, 0x40404040u, i0);          // 0x40 x4, 0x80, 0 x4
+    b.z1 = __builtin_amdgcn_perm(0x00000080u, 0x40404040u, i1);
+}
+__device__ __forceinline__ void potts_steps(uint2 bd, CompactPottsBulk &b) {
+    b.k0 = bd.x ^ 0x80808080u;
+    b.k1 = bd.y ^ 0x80808080u;
+}
+__device__ __forceinline__ int32_t row_step(const CompactPottsBulk &b, bool left_flipped, int j) {
+    return 8 * (left_flipped ? sbyte(b.k1, j) : sbyte(b.k0, j));
+}
+
+// Exact recomputation of one dword of the compact Potts walker (see
+// redo_compact_dword): rows R = tab0 + 8 k - 247, full thresholds
+// T32[k][dk + 4], and the acceptance draws of dword dw: words 1 and 3 of the
+// blocks 2 dw (sites 0, 1) and 2 dw + 1 (sites 2, 3).  The flip record holds
+// 0xff in byte j for an accepted site j.
+__device__ __noinline__ RedoResult redo_compact_potts(uint32_t R, uint32_t C, uint32_t acc_in, uint32_t ca0,
+                                                      uint32_t ca1, uint32_t ck0, uint32_t ck1, uint32_t cz0,
+                                                      uint32_t cz1, uint32_t na0, uint32_t na1, uint32_t u0,
+                                                      uint32_t u1, uint32_t u2, uint32_t u3, uint32_t tab0,
+                                                      const uint32_t *table, uint32_t dw, uint32_t sweep,
+                                                      uint32_t chain, uint32_t seed_lo, uint32_t seed_hi) {
+    const g_u32 *T = (const g_u32 *)table;
+    bool acc = acc_in != 0;
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t Rj = acc ? C : R;
+        const int32_t dk = acc ? sbyte(ck1, j) : sbyte(ck0, j);
+        const uint32_t code = acc ? ubyte(ca1, j) : ubyte(ca0, j);
+        const uint32_t z = acc ? ubyte(cz1, j) : ubyte(cz0, j);
+        const uint32_t t = lds_ld16(Rj + code) ^ (z << 8);
+        const uint32_t a = (j == 0) ? u0 : (j == 1) ? u1 : (j == 2) ? u2 : u3;
+        bool ok;
+        if (a != t) {
+            ok = a < t;
+        } else {
+            const int k = (int)((Rj + kPottsCompactBias - tab0) >> 3);
+            const uint32_t Tf = T[k * 9 + 4 + dk];
+            const uint4 b = philox4x32_10(2u * dw + (uint32_t)(j >> 1), sweep, chain, 0u, seed_lo, seed_hi);
+            ok = min((j & 1) ? b.w : b.y, 0xFFFFFFFEu) < Tf;
+        }
+        R = Rj;
+        C = Rj + (uint32_t)(8 * dk);
+        acc = ok;
+        if (ok) f |= 0xFFu << (8 * j);
+    }
+    RedoResult r;
+    r.s = FastState{R, C, lds_ld16(R + na0), lds_ld16(C + na1), acc};
+    r.f = f;
+    return r;
+}
+
+__device__ __forceinline__ RedoResult compact_redo(const FastState &s0, const CompactPottsBulk &b,
+                                                   const CompactPottsBulk &nb, const uint4 &u, const CompactExact &ex) {
+    return redo_compact_potts(s0.R, s0.C, s0.acc ? 1u : 0u, b.a0, b.a1, b.k0, b.k1, b.z0, b.z1, ubyte(nb.a0, 0),
+                              ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain,
+                              ex.seed_lo, ex.seed_hi);
+}
+
+template <int L, bool WIDE, bool COMPACT>
 __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                uint32_t sweep0, const LdsPlan &plan) {
     constexpr int W = L / 4;
@@ -1380,16 +1486,41 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
     constexpr int CDW = RPC * W;
     constexpr int NCH = L / RPC;
     constexpr int P = fast_lane_stride(L);
-    constexpr uint32_t ROWB = 36u;            // table row: nine words
+    constexpr uint32_t ROWB = COMPACT ? 8u : 36u;   // table row: four u16 pairs, or nine words
     static_assert(L % RPC == 0 && W >= 4, "fast walker shape");
+    using Bulk = typename std::conditional<COMPACT, CompactPottsBulk, PottsBulk>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nthreads = blockDim.x;
     const int nch = it.nchains;
     const bool active = (wave == 0) && (lane < nch);
     const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
-    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab + (COMPACT ? kPottsCompactGuard : 0u);
     const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
     const uint32_t ringu0 = lbase + (uint32_t)plan.off_ring;                    // [3][lane][CDW+1] uint4
+    auto row_of = [&](int k) -> uint32_t {
+        return COMPACT ? tab0 + 8u * (uint32_t)k - kPottsCompactBias : tab0 + ROWB * (uint32_t)k;
+    };
+    auto k_of = [&](uint32_t R) -> int {
+        return COMPACT ? (int)((R + kPottsCompactBias - tab0) >> 3) : (int)((R - tab0) / ROWB);
+    };
+    auto read_t = [&](uint32_t a) -> uint32_t { return COMPACT ? lds_ld16(a) : lds_ld(a); };
+    auto maps = [&](uint2 bd, Bulk &b) {
+        if constexpr (COMPACT) potts_maps_c(bd, b);
+        else potts_maps_a(bd, b);
+    };
+
+    if constexpr (COMPACT) {
+        // the pair table from the 32-bit table in HBM (rows k, columns dk + 4)
+        const g_u32 *T = (const g_u32 *)p.table;
+        const int rows = 2 * p.N + 1;
+        if (tid == 0) *(lds_u16 *)(size_t)tab0 = 0;
+        for (int e = tid; e < 4 * rows; e += nthreads) {
+            const int k = e >> 2, j = (e & 3) + 1;
+            uint16_t v = 0;
+            if (k + j < rows) v = compact_entry(T[k * 9 + 4 + j], T[(k + j) * 9 + 4 - j]);
+            *(lds_u16 *)(size_t)(tab0 + 2u + 2u * (uint32_t)e) = v;
+        }
+    }
     const uint32_t ubuf = (uint32_t)nch * (CDW + 1) * 16u;
     const uint32_t ringp0 = ringu0 + 3u * ubuf;                                 // [3][lane][CDW+1] uint4
 
@@ -1419,8 +1550,11 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
             const uint32_t t0 = (uint32_t)(((uint64_t)b0.x * 7u) >> 32), t1 = (uint32_t)(((uint64_t)b0.z * 7u) >> 32);
             const uint32_t t2 = (uint32_t)(((uint64_t)b1.x * 7u) >> 32), t3 = (uint32_t)(((uint64_t)b1.z * 7u) >> 32);
             const uint32_t off = (uint32_t)(c * (CDW + 1) + q);
-            lds_st4(bu + off * 16u, make_uint4(min(b0.y, 0xFFFFFFFEu), min(b0.w, 0xFFFFFFFEu),
-                                               min(b1.y, 0xFFFFFFFEu), min(b1.w, 0xFFFFFFFEu)));
+            uint4 acc_words = make_uint4(min(b0.y, 0xFFFFFFFEu), min(b0.w, 0xFFFFFFFEu), min(b1.y, 0xFFFFFFFEu),
+                                         min(b1.w, 0xFFFFFFFEu));
+            // the compact walker compares the top 14 bits
+            if (COMPACT) acc_words = make_uint4(acc_words.x >> 18, acc_words.y >> 18, acc_words.z >> 18, acc_words.w >> 18);
+            lds_st4(bu + off * 16u, acc_words);
             // lattice terms of the dword (row y, dword x of chain c)
             const int r = q / W, x = q - r * W;
             const int y = ci * RPC + r;
@@ -1449,7 +1583,7 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
 
     FastState st{0, 0, 0, 0, false};
     uint4 u_next = make_uint4(0, 0, 0, 0);
-    PottsBulk nb{0, 0, 0, 0, 0, 0};
+    Bulk nb{};
     // the row above, as updated in this sweep: the walker's own stores
     uint32_t upr[W];
 #pragma unroll
@@ -1458,7 +1592,7 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
 #pragma unroll
         for (int w = 0; w < W; ++w) upr[w] = lds_ld(row_addr(L - 1) + 4u * w);
         const int k = ((const g_i32 *)p.k)[it.chain0 + lane];
-        st.R = tab0 + ROWB * (uint32_t)k;
+        st.R = row_of(k);
         st.C = st.R;
         const uint32_t r0 = row_addr(0), rl = row_addr(L - 1);
         // dword 0 of chunk 0 (a row start): the producer's terms and the up row
@@ -1466,18 +1600,20 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
         const uint32_t c0 = lds_ld(r0);
         uint2 bd0 = potts_up(c0, lds_ld(rl), pe0);
         bd0.y += 1u;   // a row start: its table entry is 1 whatever the left proposal
-        potts_maps_a(bd0, nb);
+        maps(bd0, nb);
         potts_steps(bd0, nb);
         nb.cur = c0;
         nb.sp = pe0.w;
-        st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
+        st.tA = read_t(st.R + ubyte(nb.a0, 0));
         st.tB = st.tA;
     }
 
     for (int t = 0; t < total_chunks; ++t) {
         if (wave == 0) {
             if (active) {
-                const int ci = t % NCH;
+                const int sw = t / NCH;
+                const int ci = t - sw * NCH;
+                const uint32_t sweep = sweep0 + (uint32_t)sw;
                 const uint32_t ub = rbu + (uint32_t)(t % 3) * ubuf;
                 const uint32_t pb = rbp + (uint32_t)(t % 3) * ubuf;
                 const uint32_t pbn = rbp + (uint32_t)((t + 1) % 3) * ubuf;   // next chunk's lattice terms
@@ -1489,7 +1625,7 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
                     const uint32_t vnc = row_addr(yn);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        const PottsBulk b = nb;
+                        const Bulk b = nb;
                         const uint4 u = (r == 0 && w == 0) ? lds_ld4(ub) : u_next;
                         // the next dword's bulk, in pieces between this dword's sites
                         uint32_t ncur = 0, nup = 0, first = 0;
@@ -1514,20 +1650,27 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
                                 if (w + 2 == W) bd = potts_row_end(bd, ncur, pe.w, first);
                             } else if (j == 2) {
                                 bd.y = potts_left(bd.y, pe.z, b.sp);
-                                potts_maps_a(bd, nb);
+                                maps(bd, nb);
                             } else {
                                 potts_steps(bd, nb);
                                 nb.cur = ncur;
                                 nb.sp = pe.w;
                             }
                         };
-                        const uint32_t mask = walk_dword<PottsBulk, 0xFFu, 8>(st, b, nb, u, work);
+                        uint32_t mask;
+                        if constexpr (COMPACT) {
+                            const CompactExact ex{tab0, p.table, (uint32_t)(y * W + w), sweep,
+                                                  (uint32_t)(it.chain0 + lane), p.seed_lo, p.seed_hi};
+                            mask = walk_dword_compact<Bulk, 0xFFu, 8>(st, b, nb, u, work, ex);
+                        } else {
+                            mask = walk_dword<Bulk, 0xFFu, 8>(st, b, nb, u, work);
+                        }
                         upr[w] = (mask & b.sp) | (~mask & b.cur);
                         lds_st(vcur + 4 * w, upr[w]);
                     }
                     if (y == L - 1 && l.record != kRecNone) {
                         const uint32_t Rk = st.acc ? st.C : st.R;
-                        const int k = (int)((Rk - tab0) / ROWB);
+                        const int k = k_of(Rk);
                         g_i32 *h = (g_i32 *)p.hist;
                         h[(int64_t)k * p.C + it.chain0 + lane] += 1;
                     }
@@ -1541,7 +1684,7 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
 
     if (active) {
         const uint32_t Rk = st.acc ? st.C : st.R;
-        ((g_i32 *)p.k)[it.chain0 + lane] = (int)((Rk - tab0) / ROWB);
+        ((g_i32 *)p.k)[it.chain0 + lane] = k_of(Rk);
         ((g_i32 *)p.m)[it.chain0 + lane] = 0;
     }
     __syncthreads();
@@ -1559,14 +1702,15 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
 __device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                             const SweepLaunch &l, uint32_t sweep0,
                                                             const LdsPlan &plan) {
-    const bool wide = potts_wide(it.nchains);
+    const bool wide = potts_wide_item(p, it);
     switch (p.L) {
-    case 16: wide ? run_potts_fast<16, true>(p, it, lds, l, sweep0, plan)
-                  : run_potts_fast<16, false>(p, it, lds, l, sweep0, plan); return true;
-    case 24: wide ? run_potts_fast<24, true>(p, it, lds, l, sweep0, plan)
-                  : run_potts_fast<24, false>(p, it, lds, l, sweep0, plan); return true;
-    case 32: wide ? run_potts_fast<32, true>(p, it, lds, l, sweep0, plan)
-                  : run_potts_fast<32, false>(p, it, lds, l, sweep0, plan); return true;
+    case 16: wide ? run_potts_fast<16, true, false>(p, it, lds, l, sweep0, plan)
+                  : run_potts_fast<16, false, false>(p, it, lds, l, sweep0, plan); return true;
+    case 24: wide ? run_potts_fast<24, true, false>(p, it, lds, l, sweep0, plan)
+                  : run_potts_fast<24, false, false>(p, it, lds, l, sweep0, plan); return true;
+    case 32: wide ? run_potts_fast<32, true, false>(p, it, lds, l, sweep0, plan)
+                  : run_potts_fast<32, false, false>(p, it, lds, l, sweep0, plan); return true;
+    case 48: run_potts_fast<48, true, true>(p, it, lds, l, sweep0, plan); return true;
     default: return false;
     }
 }
@@ -1587,8 +1731,9 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     TabRef<TAB_LDS> tab;
     if constexpr (TAB_LDS) {
         tab.base = lbase + (uint32_t)plan.off_tab;
-        // the compact-table walker builds its own (smaller) table in LDS
-        if (!(compact_ising(p) && fast_ising_ok(p, l.n_producer_waves))) {
+        // the compact-table walkers build their own (smaller) table in LDS
+        if (!(compact_ising(p) && fast_ising_ok(p, l.n_producer_waves)) &&
+            !(compact_potts(p) && fast_potts_ok(p, l.n_producer_waves))) {
             const int n = p.trows * p.tcols;
             for (int j = tid; j < n; j += nthreads) lds_st(tab.base + 4u * (uint32_t)j, ((const g_u32 *)p.table)[j]);
         }

@@ -123,3 +123,72 @@ def test_compact_walker_at_both_ends_of_the_energy_range(L):
         kk = ctx.k()
         print(f"  k after 120 sweeps: {kk.min()}..{kk.max()} of 0..{2 * N}", flush=True)
         assert kk[:12].max() < N // 2 and kk[12:].min() > 3 * N // 2
+
+
+# ---------------------------------------------------------------- 8-state Potts L = 48
+
+@pytest.mark.parametrize("chains,cw", [(40, 32), (20, 16), (35, 35)], ids=["c40-cw32", "c20-cw16", "c35-cw35"])
+def test_compact_potts_walker_iterations_bit_exact(chains, cw):
+    """8-state Potts L = 48 with the compact table: weight iterations with the
+    correction function, every per-chain and merged histogram, weight, table
+    and state bit for bit."""
+    from workloads import POTTS
+    import paper_1212_3975_amd as pm
+    prob = Problem(POTTS, 48, chains, 500 + chains, q=8)
+    with pm.Muca([prob], correction=1, chains_per_wg=cw, **PLACED) as ctx:
+        info = ctx.launch_info()
+        print("launch", info, flush=True)
+        assert info["fast_walker"] == 1 and info["chains_per_wg"] == cw
+        orc = oracle.OracleRun(prob.model, 48, chains, prob.seed, q=8)
+        for it in range(4):
+            ctx.sweep(150, pm.REC_MUCA)
+            ch = ctx.chain_hist()
+            st = ctx.merge_update(True)[0]
+            H, fl, per_chain = orc.iterate(150, correct=True)
+            print(f"  iteration {it}: visited {fl.visited}", flush=True)
+            assert np.array_equal(ch, per_chain), f"per-chain histograms differ at iteration {it}"
+            assert np.array_equal(ctx.H(), H) and st["visited"] == fl.visited
+            assert _same_bits(ctx.lnW(), orc.lnW)
+            assert np.array_equal(ctx.table(), device_table(orc))
+            _compare(ctx, orc)
+
+
+def test_compact_potts_walker_production_and_both_ends():
+    """Production counts bit for bit, from chains started in ground states
+    (k = 0, one colour) and two-colour checkerboards (k = 2N), under weights
+    that favour both ends, lnW(k) = 1.5 |k - N| (canonical at beta = 1.5 on
+    either side, beyond the transition at 1.3425)."""
+    from workloads import POTTS
+    import paper_1212_3975_amd as pm
+    L = 48
+    prob = Problem(POTTS, L, 24, 777, q=8)
+    N = L * L
+    k = np.arange(2 * N + 1)
+    lnW = 1.5 * np.abs(k - N).astype(np.float64)
+    x, y = np.meshgrid(np.arange(L), np.arange(L))
+    board = ((x + y) % 2).astype(np.uint8).ravel()
+    spins = np.zeros((prob.n_chains, N), np.uint8)
+    for c in range(12):
+        spins[c] = c % 8                                # ground states of several colours
+    for c in range(12, 24):
+        spins[c] = np.where(board == 1, c % 8, (c + 3) % 8)   # two-colour checkerboards
+    with pm.Muca([prob], chains_per_wg=32, **PLACED) as ctx:
+        assert ctx.launch_info()["fast_walker"] == 1
+        ctx.restore(_checkpoint_with_spins(ctx, prob, spins))
+        ctx.set_log_weights(0, lnW)
+        kk = ctx.k()
+        assert np.all(kk[:12] == 0) and np.all(kk[12:] == 2 * N)
+        orc = oracle.OracleRun(prob.model, L, prob.n_chains, prob.seed, q=8)
+        orc.spins[:] = spins
+        for c in range(prob.n_chains):
+            orc.k[c], orc.m[c] = oracle.energy(POTTS, L, orc.spins[c])
+        orc.set_log_weights(lnW)
+        ctx.clear_production()
+        ctx.sweep(30, pm.REC_NONE)
+        ctx.sweep(120, pm.REC_PROD)
+        cnt, _ = orc.production(30, 120)
+        assert np.array_equal(ctx.prod_counts(), cnt)
+        _compare(ctx, orc)
+        kk = ctx.k()
+        print(f"  k after 150 sweeps: {kk.min()}..{kk.max()} of 0..{2 * N}", flush=True)
+        assert kk[:12].max() < N // 2 and kk[12:].min() > 3 * N // 2
