@@ -925,11 +925,58 @@ __device__ __forceinline__ int32_t row_step(const CompactBulk &b, bool left_flip
     return left_flipped ? sbyte(b.e1, j) : sbyte(b.e0, j);
 }
 
-// Walker state and flip record of an exactly recomputed dword.
-struct RedoResult {
-    FastState s;
-    uint32_t f;
+// Walker state of the compact walkers: as FastState, with the previous
+// site's outcome in a full word (a struct without padding stays in registers
+// through the copies the exact redo makes).
+struct CompactState {
+    uint32_t R, C, tA, tB, acc;
 };
+
+// t with its byte 1 xored with byte j of codes (the compact walkers' decode of
+// a table entry), in one SDWA instruction; j is a compile-time constant after
+// unrolling.
+__device__ __forceinline__ uint32_t xor_byte1(uint32_t t, uint32_t codes, int j) {
+    uint32_t r = t;
+    switch (j) {
+    case 0:
+        asm("v_xor_b32_sdwa %0, %1, %2 dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_0"
+            : "+v"(r) : "v"(t), "v"(codes));
+        break;
+    case 1:
+        asm("v_xor_b32_sdwa %0, %1, %2 dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_1"
+            : "+v"(r) : "v"(t), "v"(codes));
+        break;
+    case 2:
+        asm("v_xor_b32_sdwa %0, %1, %2 dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_2"
+            : "+v"(r) : "v"(t), "v"(codes));
+        break;
+    default:
+        asm("v_xor_b32_sdwa %0, %1, %2 dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_3"
+            : "+v"(r) : "v"(t), "v"(codes));
+        break;
+    }
+    return r;
+}
+
+// Walker state and flip record of an exactly recomputed dword: R, C, tA, tB,
+// acc (0/1) and the flip record, as a vector so that the out-of-line redo
+// returns it in registers (a returned struct can be placed in memory and drag
+// the walker's state there with it).
+typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
+typedef u32x8 RedoResult;
+__device__ __forceinline__ RedoResult redo_result(uint32_t R, uint32_t C, uint32_t tA, uint32_t tB, bool acc,
+                                                  uint32_t f) {
+    RedoResult r;
+    r.s0 = R;
+    r.s1 = C;
+    r.s2 = tA;
+    r.s3 = tB;
+    r.s4 = acc ? 1u : 0u;
+    r.s5 = f;
+    r.s6 = 0u;
+    r.s7 = 0u;
+    return r;
+}
 
 // Exact recomputation of one dword of the compact walker (rare: some site of
 // the dword drew a prefix equal to its entry's).  From the state at the
@@ -973,10 +1020,7 @@ __device__ __noinline__ RedoResult redo_compact_dword(uint32_t R, uint32_t C, ui
         acc = ok;
         if (ok) f |= 1u << j;
     }
-    RedoResult r;
-    r.s = FastState{R, C, lds_ld16(R + na0), lds_ld16(C + na1), acc};
-    r.f = f;
-    return r;
+    return redo_result(R, C, lds_ld16(R + na0), lds_ld16(C + na1), acc, f);
 }
 
 // The four sites of one dword against the compact table; as walk_dword, plus
@@ -990,17 +1034,18 @@ struct CompactExact {
     uint32_t blk, sweep, chain, seed_lo, seed_hi;
 };
 
-__device__ __forceinline__ RedoResult compact_redo(const FastState &s0, const CompactBulk &b, const CompactBulk &nb,
-                                                   const uint4 &u, const CompactExact &ex) {
-    return redo_compact_dword(s0.R, s0.C, s0.acc ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1, ubyte(nb.a0, 0),
+__device__ __forceinline__ RedoResult compact_redo(uint32_t R0, uint32_t C0, bool acc0, const CompactBulk &b,
+                                                   const CompactBulk &nb, const uint4 &u, const CompactExact &ex) {
+    return redo_compact_dword(R0, C0, acc0 ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1, ubyte(nb.a0, 0),
                               ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain,
                               ex.seed_lo, ex.seed_hi);
 }
 
 template <class Bulk, uint32_t FLIP, int STRIDE, class Work>
-__device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const Bulk &b, const Bulk &nb, const uint4 &u,
+__device__ __forceinline__ uint32_t walk_dword_compact(CompactState &s, const Bulk &b, const Bulk &nb, const uint4 &u,
                                                        Work &&work, const CompactExact &ex) {
-    const FastState s0 = s;
+    const uint32_t R0 = s.R, C0 = s.C;   // the state at the dword's start, for an exact redo
+    const bool acc0 = s.acc != 0u;
     uint32_t f = 0;
     bool tie = false;
 #pragma unroll
@@ -1012,8 +1057,8 @@ __device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const Bulk 
         const uint32_t nA = lds_ld16(Rj + a0);
         const uint32_t nB = lds_ld16(Cj + a1);
         __builtin_amdgcn_sched_barrier(0);
-        const uint32_t tA = s.tA ^ (ubyte(b.z0, j) << 8);
-        const uint32_t tB = s.tB ^ (ubyte(b.z1, j) << 8);
+        const uint32_t tA = xor_byte1(s.tA, b.z0, j);
+        const uint32_t tB = xor_byte1(s.tB, b.z1, j);
         const uint32_t tj = s.acc ? tB : tA;
         const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
         s.acc = uj < tj;
@@ -1031,9 +1076,13 @@ __device__ __forceinline__ uint32_t walk_dword_compact(FastState &s, const Bulk 
     if (tie) {
         // the exact redo writes the flip record in the walker's format
         // (FLIP << STRIDE j for an accepted site j)
-        const RedoResult r = compact_redo(s0, b, nb, u, ex);
-        s = r.s;
-        f = r.f;
+        const RedoResult r = compact_redo(R0, C0, acc0, b, nb, u, ex);
+        s.R = r.s0;
+        s.C = r.s1;
+        s.tA = r.s2;
+        s.tB = r.s3;
+        s.acc = r.s4;
+        f = r.s5;
     }
     return f;
 }
@@ -1109,7 +1158,8 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
         }
     };
 
-    FastState st{0, 0, 0, 0, false};
+    using State = typename std::conditional<COMPACT, CompactState, FastState>::type;
+    State st{};
     Bulk nb{};
     if (active) {
         // ring: rows L-1, 0, 1 (row 2 is unpacked while row 0 is updated)
@@ -1131,7 +1181,7 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
 
     // producers: chunk t covers dwords (t mod NCH) * CDW .. + CDW - 1 of sweep t / NCH;
     // the compact walker receives the top 14 bits of each clamped draw
-    auto produce = [&](int t) {
+    auto produce = [&](int t) __attribute__((always_inline)) {
         const int sw = t / NCH;
         const uint32_t sweep = sweep0 + (uint32_t)sw;
         const int blk0 = (t - sw * NCH) * CDW;
@@ -1155,7 +1205,7 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
     // One chunk of 32 sites (bit dword H of row y); H is a compile-time
     // constant so that every dword index, LDS offset and flip word below is
     // fixed at compile time.
-    auto walk_chunk = [&](auto HC, int t) {
+    auto walk_chunk = [&](auto HC, int t) __attribute__((always_inline)) {
         constexpr int H = decltype(HC)::value;
         const int sw = t / NCH;
         const int y = (t - sw * NCH) / BPR;
@@ -1176,7 +1226,7 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
             uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;
             BulkSums ns{0, 0, 0};
             BulkDiff nd{0, 0, 0};
-            auto work = [&](int j) {
+            auto work = [&](int j) __attribute__((always_inline)) {
                 if (j == 0) {
                     if (q + 1 < CDW) u_next = lds_ld4(ub + (uint32_t)(q + 1) * 16u);
                     if (w + 1 < W) {
@@ -1236,7 +1286,7 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
     };
     // chunk H of a row, then the barrier that hands the next chunk's random
     // words over
-    auto chunk_pass = [&](auto HC, int t) {
+    auto chunk_pass = [&](auto HC, int t) __attribute__((always_inline)) {
         constexpr int H = decltype(HC)::value;
         if (wave == 0) {
             if (active) walk_chunk(IntConst<H>{}, t + H);
@@ -1464,15 +1514,12 @@ __device__ __noinline__ RedoResult redo_compact_potts(uint32_t R, uint32_t C, ui
         acc = ok;
         if (ok) f |= 0xFFu << (8 * j);
     }
-    RedoResult r;
-    r.s = FastState{R, C, lds_ld16(R + na0), lds_ld16(C + na1), acc};
-    r.f = f;
-    return r;
+    return redo_result(R, C, lds_ld16(R + na0), lds_ld16(C + na1), acc, f);
 }
 
-__device__ __forceinline__ RedoResult compact_redo(const FastState &s0, const CompactPottsBulk &b,
+__device__ __forceinline__ RedoResult compact_redo(uint32_t R0, uint32_t C0, bool acc0, const CompactPottsBulk &b,
                                                    const CompactPottsBulk &nb, const uint4 &u, const CompactExact &ex) {
-    return redo_compact_potts(s0.R, s0.C, s0.acc ? 1u : 0u, b.a0, b.a1, b.k0, b.k1, b.z0, b.z1, ubyte(nb.a0, 0),
+    return redo_compact_potts(R0, C0, acc0 ? 1u : 0u, b.a0, b.a1, b.k0, b.k1, b.z0, b.z1, ubyte(nb.a0, 0),
                               ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain,
                               ex.seed_lo, ex.seed_hi);
 }
@@ -1581,7 +1628,8 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
     const uint32_t rbp = ringp0 + (uint32_t)(lane * (CDW + 1)) * 16u;
     auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
 
-    FastState st{0, 0, 0, 0, false};
+    using State = typename std::conditional<COMPACT, CompactState, FastState>::type;
+    State st{};
     uint4 u_next = make_uint4(0, 0, 0, 0);
     Bulk nb{};
     // the row above, as updated in this sweep: the walker's own stores
