@@ -106,7 +106,13 @@ typedef struct {
  *                    k_lo with the slope between k_lo and the reachable bin L
  *                    reachable bins inward (or the far edge if the region is
  *                    narrower), likewise above k_hi (the correction function
- *                    of Sec. 3) */
+ *                    of Sec. 3)
+ *   wait_polls       polls of the bounded waits between a streamed walker
+ *                    and its helper waves before they give up (0 = default,
+ *                    2^24, a second or more; negative = none, so that every
+ *                    wait gives up at once: a test of that path, after which
+ *                    mucaMergeUpdate, mucaIterate, mucaGet and mucaCheckpoint
+ *                    report MUCA_EHIP).  Not a step of the method. */
 typedef struct {
     int32_t chains_per_wg;
     int32_t rng_mode;
@@ -118,7 +124,7 @@ typedef struct {
     int32_t flat_rule;
     int32_t tune_sweeps;
     int32_t correction;
-    int32_t pad;
+    int32_t wait_polls;
 } muca_options;
 
 /* Statistics of one weight iteration for one problem, from the merged
@@ -138,7 +144,9 @@ typedef struct {
     int32_t chains_per_wg, rng_mode, spin_placement, table_placement;
     int32_t lds_bytes, n_workgroups;
     int32_t fast_walker;   /* 1: a four-sites-per-step walker (Ising, multimagnetic or 8-Potts) runs it */
-    int32_t pad1;
+    int32_t walker;        /* walker of the problem's first work item: 0 generic, 1 byte-wise Ising or
+                              multimagnetic, 2 packed Ising, 3 packed Ising on the compact table,
+                              4 8-Potts, 5 8-Potts on the compact table, 6 streamed Ising */
 } muca_launch_info;
 
 /* Bytes of device workspace that mucaInit needs for these problems.  (Not a

@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("spin_placement", ctypes.c_int32), ("table_placement", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("production", ctypes.c_int32),
                 ("flat_ratio", ctypes.c_double), ("flat_rule", ctypes.c_int32),
-                ("tune_sweeps", ctypes.c_int32), ("correction", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("tune_sweeps", ctypes.c_int32), ("correction", ctypes.c_int32), ("wait_polls", ctypes.c_int32)]
 
 
 class IterStats(ctypes.Structure):
@@ -59,7 +59,7 @@ class LaunchInfo(ctypes.Structure):
     _fields_ = [("chains_per_wg", ctypes.c_int32), ("rng_mode", ctypes.c_int32),
                 ("spin_placement", ctypes.c_int32), ("table_placement", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
-                ("fast_walker", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+                ("fast_walker", ctypes.c_int32), ("walker", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("pad")}

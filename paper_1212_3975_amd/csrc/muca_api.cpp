@@ -218,7 +218,7 @@ Layout plan_layout(const muca_problem *pr, int32_t n, const muca_options &o) {
     L.off_probdev = take(sizeof(ProbDev) * n);
     L.off_items = take(sizeof(WorkItem) * L.max_items);
     L.off_merge = take(sizeof(MergeItem) * L.n_merge);
-    L.off_sweep = take(sizeof(uint32_t));
+    L.off_sweep = take(2 * sizeof(uint32_t));   // sweep counter, status word
     L.off_betas = take(sizeof(double) * kMaxBetas);
     L.off_rwout = take(sizeof(double) * 3 * kMaxBetas);
     L.off_tables = take(4 * L.tab_words);
@@ -436,6 +436,19 @@ muca_status check_sweeps(muca_ctx ctx, int64_t n_sweeps) {
     return MUCA_OK;
 }
 
+// The status word of the sweep launches (after the stream has drained): a
+// walker whose bounded wait for its producer waves expired (or theirs for it)
+// has left the chains in an invalid state.  The word stays set.
+muca_status check_walk_status(muca_ctx ctx) {
+    uint32_t w = 0;
+    HIPCHECK(ctx, hipMemcpyAsync(&w, ctx->d_sweep + 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (w & kStatusWaitExpired)
+        return fail(ctx, MUCA_EHIP, "a sweep's bounded wait between walker and producer waves expired; "
+                                    "the chains' state is not valid");
+    return MUCA_OK;
+}
+
 muca_status enqueue_sweep(muca_ctx ctx, int64_t n_sweeps, int record, bool timed) {
     SweepLaunch l;
     l.probs = ctx->d_probs;
@@ -446,6 +459,8 @@ muca_status enqueue_sweep(muca_ctx ctx, int64_t n_sweeps, int record, bool timed
     l.n_sweeps = (int)n_sweeps;
     l.record = record;
     l.sweep_ctr = ctx->d_sweep;
+    l.status = ctx->d_sweep + 1;
+    l.wait_polls = ctx->opt.wait_polls == 0 ? (1u << 24) : ctx->opt.wait_polls < 0 ? 0u : (uint32_t)ctx->opt.wait_polls;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         if (ctx->event_pool.size() < 2) {
@@ -869,7 +884,7 @@ muca_status mucaInit(muca_ctx *out, const muca_problem *problems, int32_t n, con
     }
     if ((st = upload_probdev(ctx))) return bail(st);
     // zero accumulators, counter and tables; draw the initial state
-    INITCHECK(launch_fill_u32(ctx->d_sweep, 0u, 1, ctx->stream));
+    INITCHECK(launch_fill_u32(ctx->d_sweep, 0u, 2, ctx->stream));
     for (size_t pi = 0; pi < ctx->probs.size(); ++pi) {
         const ProbHost &h = ctx->probs[pi];
         const ProbDev &d = ctx->h_probdev[pi];
@@ -938,6 +953,7 @@ muca_status mucaMergeUpdate(muca_ctx ctx, int32_t update, muca_iter_stats *out) 
     if (st) return st;
     HIPCHECK(ctx, hipMemcpyAsync(ctx->pin_H, ctx->d_H, 8 * ctx->h_words, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if ((st = check_walk_status(ctx))) return st;
     host_update(ctx, update);
     if (update) {
         if ((st = upload_tables(ctx))) return st;
@@ -993,6 +1009,7 @@ muca_status mucaIterate(muca_ctx ctx, int64_t n_sweeps, muca_iter_stats *out) {
     HIPCHECK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->sweep += (uint32_t)n_sweeps;
+    if ((cs = check_walk_status(ctx))) return cs;
     if (out)
         for (size_t i = 0; i < ctx->probs.size(); ++i) out[i] = ctx->probs[i].last;
     return MUCA_OK;
@@ -1073,7 +1090,7 @@ muca_status mucaGet(muca_ctx ctx, int32_t what, int32_t prob, void *dst, size_t 
     auto d2h = [&](const void *src, size_t n) -> muca_status {
         HIPCHECK(ctx, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
-        return MUCA_OK;
+        return check_walk_status(ctx);
     };
     switch (what) {
     case MUCA_GET_H:
@@ -1137,6 +1154,11 @@ muca_status mucaLaunchInfo(muca_ctx ctx, int32_t prob, muca_launch_info *info) {
     for (auto &it : ctx->items) n += (it.prob == prob);
     info->n_workgroups = n;
     info->fast_walker = uses_fast_walker(ctx->h_probdev[prob], ctx->n_producer_waves) ? 1 : 0;
+    for (auto &it : ctx->items)
+        if (it.prob == prob) {
+            info->walker = walker_kind(ctx->h_probdev[prob], it, ctx->n_producer_waves);
+            break;
+        }
     return MUCA_OK;
 }
 
@@ -1203,6 +1225,8 @@ muca_status mucaCheckpoint(muca_ctx ctx, void *blob, size_t *bytes) {
         o += 4 * (size_t)p.nbins * C;
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    muca_status st = check_walk_status(ctx);
+    if (st) return st;
     *bytes = need;
     return MUCA_OK;
 }

@@ -61,7 +61,12 @@ struct SweepLaunch {
     int32_t n_sweeps;
     int32_t record;
     const uint32_t *sweep_ctr;  // device word: sweep number of the first sweep
+    uint32_t *status;           // device word, sticky: bit 0 set when a walker's bounded wait expired
+    uint32_t wait_polls;        // polls of those bounded waits
 };
+
+// Bits of the sweep status word.
+constexpr uint32_t kStatusWaitExpired = 1u;
 
 // LDS bytes one work item needs (table, lattice, random-word ring).
 int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves);
@@ -70,6 +75,8 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves);
 int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves);
 // Whether the sweep kernel takes the fast Ising walker for this problem.
 bool uses_fast_walker(const ProbDev &p, int n_producer_waves);
+// The walker that runs a work item (the codes of muca_launch_info.walker).
+int walker_kind(const ProbDev &p, const WorkItem &it, int n_producer_waves);
 // Raises the dynamic-LDS limit of the sweep kernel.
 hipError_t configure_sweep_kernel(int max_lds_bytes);
 

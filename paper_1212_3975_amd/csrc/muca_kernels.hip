@@ -93,6 +93,7 @@ __host__ __device__ inline int round_up(int v, int a) { return (v + a - 1) / a *
 struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
     int off_rows;   // packed Ising walker only: the ring of unpacked rows
+    int off_ctr;    // streamed Ising walker only: progress counters
 };
 // The packed Ising walker: L = 64 with more than 16 chains per workgroup
 // (32-bit table), and L = 96 and 128 with the compact table below.  A lane's
@@ -132,6 +133,18 @@ __host__ __device__ inline bool potts_wide_item(const ProbDev &p, const WorkItem
     return potts_wide(it.nchains) || compact_potts(p);
 }
 __host__ __device__ constexpr int fast_lane_stride(int L) { return ((L * L / 4) % 2) ? L * L / 4 : L * L / 4 + 1; }
+// The streamed Ising walker (run_ising_stream): L = 64 with up to 16 chains
+// per workgroup.  Its producers form every dword's complete bulk and hand it
+// over through a per-lane ring of one row of 32-byte records (the dword's four
+// acceptance words, then its column maps and row steps), with a 16-byte pad
+// per lane so that the lanes' 16-byte reads fall in distinct banks.
+constexpr int kStreamBatch = 4;   // dwords per progress report and per producer batch
+constexpr int kStreamCheck = 1;   // batches the walker checks at once
+constexpr int kStreamCtrWords = 8;
+__host__ __device__ constexpr int stream_lane_words(int L) { return (L / 4) * 8 + 4; }
+__host__ __device__ inline bool stream_ising(const ProbDev &p, const WorkItem &it) {
+    return p.model == kIsing && p.L == 64 && it.nchains <= 16;
+}
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
     l.off_tab = 0;
@@ -144,10 +157,18 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
                                16);
     l.off_spin = l.off_tab + tab;
     l.off_rows = 0;
+    l.off_ctr = 0;
     if (fast_ising_ok(p, n_producer_waves) && packed_ising(p, it)) {
         l.off_rows = l.off_spin + round_up(it.nchains * packed_bit_stride(p.L) * 4, 16);
         l.off_ring = l.off_rows + round_up(it.nchains * packed_row_stride(p.L) * 4, 16);
         l.total = l.off_ring + 2 * it.nchains * (kPackedChunkDwords + 1) * 16;
+        return l;
+    }
+    if (fast_ising_ok(p, n_producer_waves) && stream_ising(p, it)) {
+        // lane-major lattice with an odd dword stride; record rings; counters
+        l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
+        l.off_ctr = l.off_ring + it.nchains * stream_lane_words(p.L) * 4;
+        l.total = l.off_ctr + 4 * kStreamCtrWords;
         return l;
     }
     if (fast_ising_ok(p, n_producer_waves)) {
@@ -208,6 +229,16 @@ __host__ __device__ inline bool fast_potts_ok(const ProbDev &p, int n_producer_w
 
 bool uses_fast_walker(const ProbDev &p, int n_producer_waves) {
     return fast_ising_ok(p, n_producer_waves) || fast_potts_ok(p, n_producer_waves);
+}
+
+int walker_kind(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
+    if (fast_ising_ok(p, n_producer_waves)) {
+        if (p.model == kIsing && packed_ising(p, it)) return compact_ising(p) ? 3 : 2;
+        if (p.model == kIsing && stream_ising(p, it)) return 6;
+        return 1;
+    }
+    if (fast_potts_ok(p, n_producer_waves)) return compact_potts(p) ? 5 : 4;
+    return 0;
 }
 
 // Every access of the sweep kernel names its address space: LDS through
@@ -851,6 +882,347 @@ __device__ __forceinline__ void run_ising_fast(const ProbDev &p, const WorkItem 
 }
 
 
+// ------------------------------------------------------------------ streamed Ising walker
+//
+// The byte walker above still forms part of every dword's bulk itself: the
+// terms of the row above, which it is updating in the same sweep.  But dword
+// (y, w) needs only dword (y-1, w) of this sweep, which the walker finished a
+// full row (L/4 dwords) before it reaches (y, w).  Here the producer waves
+// form the complete bulk of every dword (column maps and row steps of both
+// candidates, from the dword's old spins, its left, right and lower
+// neighbours and the row above as this sweep left it) and hand it to the
+// walker in a record beside the dword's four acceptance words.  The walker
+// only decides sites, xors each dword's flips into the lattice and reports
+// its progress.
+//
+// Walker and producers exchange progress through LDS counters instead of
+// workgroup barriers:
+//   - the walker publishes, after every batch of kStreamBatch dwords, the
+//     number of dwords it has finished;
+//   - producer wave i forms the batches i, i+np, i+2np, ... of every sweep (np
+//     producer waves); the batches are published in order, on one counter of
+//     the batches formed, each wave waiting for the previous batch's.
+// A batch of row y may be formed once the walker has finished the batch's
+// dwords of row y-1; a row's last batch also needs the row's first dword (the
+// right neighbour of the row's last site, this sweep).  The producers read
+// and count everything else (the old left, right and lower neighbours, the
+// random words) before they wait.  The walker checks the next batch one
+// dword before it first reads it (the counter was read a dword earlier, so
+// the check costs no LDS wait).  Each side has several dwords of slack, so
+// neither normally waits long.  Both sides wait with a bounded poll: if one
+// expires the workgroup raises an abort word that ends every other wait, the
+// walker rewrites its records to reject every move, the workgroup finishes
+// with invalid chains and sets the launch's status word, which the host
+// reports.  LDS operations of one wave are performed in order, so a counter
+// written after data is never seen before that data.
+//
+// Records: per lane a ring of one row of 32-byte slots; slot w holds dword w
+// of the row being formed (random words, then a0, a1, e0, e1).  Slot w of row
+// y replaces slot w of row y-1 only after the walker has finished (y-1, w).
+
+__device__ __forceinline__ uint32_t lds_ld_sync(uint32_t a) {
+    return __hip_atomic_load((lds_u32 *)(size_t)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st_sync(uint32_t a, uint32_t v) {
+    __hip_atomic_store((lds_u32 *)(size_t)a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_xor(uint32_t a, uint32_t v) {
+    (void)__hip_atomic_fetch_xor((lds_u32 *)(size_t)a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Keeps the compiler from moving memory accesses across this point (the
+// hardware keeps one wave's LDS operations in order by itself).
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+// Counters of the streamed walker, LDS words from ctr: [0] batches formed
+// (published in order), [1] dwords the walker has finished, [7] abort.
+constexpr uint32_t kCtrFormed = 0u, kCtrDone = 4u, kCtrAbort = 28u;
+
+// Bounded wait, wave-uniform: polls (up to `polls` times; 2^24 polls take a
+// second or more) until the counter at ctr + off reaches want (wrap-safe).
+// Returns false at once if the abort word is raised; raises it and returns
+// false if the count is not reached.
+__device__ __noinline__ bool stream_wait(uint32_t ctr, uint32_t off, uint32_t want, uint32_t polls) {
+    for (uint32_t n = 0; n < polls; ++n) {
+        if ((int32_t)(lds_ld_sync(ctr + off) - want) >= 0) {
+            lds_order();
+            return true;
+        }
+        if (lds_ld_sync(ctr + kCtrAbort)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_st_sync(ctr + kCtrAbort, 1u);
+    return false;
+}
+
+// The four sites of one dword for the streamed walker: as walk_dword, but
+// with no bulk to interleave.  Between its compare and the next site's row
+// select, which reads the compare as a lane mask, each site records the flip
+// of the previous site, whose compare is a full site old, so that the select
+// does not wait for a fresh compare.  The dword's last flip is recorded by the
+// next dword's first site, which passes the previous dword's finished flip
+// record to done() (bit 8 j for site j).  Returns the record of sites 0..2;
+// site 3's outcome is s.acc.
+template <class Work, class Done>
+__device__ __forceinline__ uint32_t walk_dword_stream(FastState &s, const FastBulk &b, const FastBulk &nb,
+                                                      const uint4 &u, uint32_t fprev, Work &&work, Done &&done) {
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t Rj = s.acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)row_step(b, s.acc, j);
+        const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
+        const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
+        const uint32_t nA = lds_ld(Rj + a0);
+        const uint32_t nB = lds_ld(Cj + a1);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t tj = s.acc ? s.tB : s.tA;
+        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+        const bool prev = s.acc;
+        s.acc = uj < tj;
+        s.R = Rj;
+        s.C = Cj;
+        s.tA = nA;
+        s.tB = nB;
+        __builtin_amdgcn_sched_barrier(0);
+        if (j == 0) {
+            done(fprev | (prev ? 0x01000000u : 0u));
+        } else {
+            f |= prev ? (1u << (8 * (j - 1))) : 0u;
+            asm volatile("" : "+v"(f));   // recorded here, not at the end of the dword
+        }
+        work(j);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return f;
+}
+
+template <int L>
+__device__ __forceinline__ void run_ising_stream(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                                                 uint32_t sweep0, const LdsPlan &plan) {
+    constexpr uint32_t RB = 20u;              // table row bytes
+    constexpr int W = L / 4;                  // dwords per row
+    constexpr int NW = L * L / 4;             // dwords per lattice
+    constexpr int P = fast_lane_stride(L);    // lattice dwords between lanes
+    constexpr int B = kStreamBatch;
+    constexpr int BPR = W / B;                // batches per row
+    constexpr int BPS = L * BPR;              // batches per sweep
+    constexpr uint32_t RS = stream_lane_words(L) * 4u;   // ring bytes per lane
+    // the walker checks batches c+1 .. c+K (K = kStreamCheck) in the last
+    // dword of every K-th batch c: by then it has finished what every record
+    // of those batches depends on (W >= (K+1) B + 1), a row's last batch
+    // included (it also needs the row's first dword)
+    constexpr int K = kStreamCheck;
+    static_assert(W % (K * B) == 0 && W >= (K + 1) * B + 1, "streamed walker shape");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthreads = blockDim.x;
+    const int np = nthreads / 64 - 1;         // producer waves
+    const int nch = it.nchains;
+    const bool active = (wave == 0) && (lane < nch);
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab;
+    const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
+    const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
+    const uint32_t ctr = lbase + (uint32_t)plan.off_ctr;   // counters (see kCtrDone)
+
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const g_u8 *g = (const g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        const uint32_t v = (uint32_t)g[0] | ((uint32_t)g[p.C] << 8) | ((uint32_t)g[2 * (int64_t)p.C] << 16) |
+                           ((uint32_t)g[3 * (int64_t)p.C] << 24);
+        lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
+    }
+    if (tid < kStreamCtrWords) lds_st(ctr + 4u * (uint32_t)tid, 0u);
+    __syncthreads();
+
+    const int n_sweeps = l.n_sweeps;
+    if (wave == 0) {
+        if (active) {
+            const uint32_t sb = spin0 + (uint32_t)(lane * P) * 4u;   // this lane's lattice
+            const uint32_t rb = ring0 + (uint32_t)lane * RS;          // this lane's records
+            auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
+            FastState st{0, 0, 0, 0, false};
+            const int k0 = ((const g_i32 *)p.k)[it.chain0 + lane];
+            st.R = tab0 + RB * (uint32_t)(k0 >> 1);
+            st.C = st.R;
+            // After a wait gives up, the walker rewrites its records to reject
+            // every move (draws 2^32 - 1, column 0, no row step) and walks them
+            // to the end of the row: nothing changes, every read stays in the
+            // table, and the loops stay free of exits.
+            auto neutralize = [&]() {
+                for (int w = 0; w < W; ++w) {
+                    lds_st4(rb + (uint32_t)w * 32u, make_uint4(~0u, ~0u, ~0u, ~0u));
+                    lds_st4(rb + (uint32_t)w * 32u + 16u, make_uint4(0u, 0u, 0u, 0u));
+                }
+            };
+            bool ok = stream_wait(ctr, kCtrFormed, 1u, l.wait_polls);   // batch 0 of the launch
+            if (!ok) neutralize();
+            uint4 u_next = lds_ld4(rb);
+            const uint4 m0 = lds_ld4(rb + 16u);
+            FastBulk nb{0, m0.x, m0.y, m0.z, m0.w};
+            st.tA = lds_ld(st.R + ubyte(nb.a0, 0));
+            st.tB = st.tA;
+            uint32_t c = 0;        // batches walked before the current one (wraps)
+            uint32_t formed = 0;   // batches formed, read a dword before the check
+            uint32_t fpend = 0;    // flips of sites 0..2 of the last dword walked, not yet in the lattice
+            uint32_t apend = sb;   // that dword's address (nothing pending before the first dword)
+            for (int s = 0; s < n_sweeps && ok; ++s) {
+                for (int y = 0; y < L && ok; ++y) {
+                    const uint32_t vcur = row_addr(y);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const int q = w % B;
+                        // in a batch's last dword (every K-th batch): batches c + 1 (whose
+                        // first record this dword's first site reads) .. c + K, none
+                        // beyond the launch; the counter was read a dword earlier
+                        const int qk = w % (K * B);
+                        if (qk == B - 2) formed = lds_ld_sync(ctr + kCtrFormed);
+                        if (qk == B - 1 && ok) {
+                            const uint32_t f1 = __builtin_amdgcn_readfirstlane(formed);
+                            uint32_t want = __builtin_amdgcn_readfirstlane(c) + (uint32_t)(K + 1);
+                            if (y == L - 1 && s + 1 == n_sweeps) {
+                                const int left = (W - 1 - w) / B;   // batches of the launch after this one
+                                if (left < K) want = __builtin_amdgcn_readfirstlane(c) + (uint32_t)(left + 1);
+                            }
+                            if ((int32_t)(f1 - want) < 0) {
+                                ok = stream_wait(ctr, kCtrFormed, want, l.wait_polls);
+                                if (!ok) neutralize();
+                            }
+                            lds_order();
+                        }
+                        const FastBulk b = nb;
+                        const uint4 u = u_next;
+                        auto work = [&](int j) {
+                            if (j == 0) {
+                                const uint32_t slot = rb + (uint32_t)((w + 1) % W) * 32u;   // dword after this one
+                                u_next = lds_ld4(slot);
+                                const uint4 m = lds_ld4(slot + 16u);
+                                nb = FastBulk{0, m.x, m.y, m.z, m.w};
+                            }
+                        };
+                        // the previous dword's flips go into the lattice; after a
+                        // batch's last dword, the walker reports the batch done
+                        auto done = [&](uint32_t fp) {
+                            lds_xor(apend, fp);
+                            if (q == 0) {
+                                lds_order();
+                                lds_st_sync(ctr + kCtrDone, c * (uint32_t)B);
+                            }
+                        };
+                        fpend = walk_dword_stream(st, b, nb, u, fpend, work, done);
+                        apend = vcur + 4u * (uint32_t)w;
+                        if (q == B - 1) ++c;
+                    }
+                    if (y == L - 1 && l.record != kRecNone) {
+                        const uint32_t Rk = st.acc ? st.C : st.R;
+                        int bin = 2 * ((int32_t)(Rk - tab0) / (int32_t)RB);
+                        bin = min(max(bin, 0), p.nbins - 1);   // in range even after an abort
+                        const int64_t cidx = (int64_t)bin * p.C + it.chain0 + lane;
+                        g_i32 *h = (g_i32 *)p.hist;
+                        h[cidx] += 1;
+                        if (l.record == kRecProd) {
+                            g_i64 *sab = (g_i64 *)p.sabs;
+                            int ones = 0;
+                            for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
+                            // the last dword's flips are still pending
+                            const uint32_t old = lds_ld(apend);
+                            const uint32_t fl = fpend | (st.acc ? 0x01000000u : 0u);
+                            ones += __builtin_popcount(old ^ fl) - __builtin_popcount(old);
+                            const int m = 2 * ones - L * L;
+                            sab[cidx] += (int64_t)(m < 0 ? -m : m);
+                        }
+                    }
+                }
+            }
+            lds_xor(apend, fpend | (st.acc ? 0x01000000u : 0u));
+            const uint32_t Rk = st.acc ? st.C : st.R;
+            ((g_i32 *)p.k)[it.chain0 + lane] = 2 * ((int32_t)(Rk - tab0) / (int32_t)RB);
+            int ones = 0;
+            for (int dd = 0; dd < NW; ++dd) ones += __builtin_popcount(lds_ld(sb + 4u * dd));
+            ((g_i32 *)p.m)[it.chain0 + lane] = 2 * ones - L * L;
+        }
+    } else {
+        // producer wave i: batch bb of every sweep with bb = i mod np; lane r
+        // forms the record of chain r / B, dword r mod B of the batch
+        const int i = wave - 1;
+        const int r = lane;
+        const bool has = r < nch * B;
+        const int cc = r / B, qq = r - cc * B;
+        const uint32_t lb = spin0 + (uint32_t)(cc * P) * 4u;
+        const uint32_t rbp = ring0 + (uint32_t)cc * RS;
+        bool ok = true;
+        for (int s = 0; s < n_sweeps && ok; ++s) {
+            const uint32_t sweep = sweep0 + (uint32_t)s;
+            for (int bb = i; bb < BPS; bb += np) {
+                const uint32_t c = (uint32_t)s * (uint32_t)BPS + (uint32_t)bb;   // batch since the launch began
+                const int y = bb / BPR, w0 = (bb - y * BPR) * B;
+                const int x = w0 + qq;
+                // everything that does not depend on the walker first: the random
+                // words, and the counts over the old left, right and lower
+                // neighbours (the right neighbour of a row's last site, the row's
+                // first site of this sweep, excepted)
+                const uint32_t rowb = lb + (uint32_t)(y * W) * 4u;
+                uint4 u = make_uint4(0, 0, 0, 0);
+                uint32_t cur = 0;
+                uint2 pre = make_uint2(0, 0);
+                if (has) {
+                    const uint4 v = philox4x32_10((uint32_t)(y * W + x), sweep, (uint32_t)(it.chain0 + cc), 0u,
+                                                  p.seed_lo, p.seed_hi);
+                    u = make_uint4(min(v.x, 0xFFFFFFFEu), min(v.y, 0xFFFFFFFEu), min(v.z, 0xFFFFFFFEu),
+                                   min(v.w, 0xFFFFFFFEu));
+                    cur = lds_ld(rowb + 4u * (uint32_t)x);
+                    const uint32_t prv = lds_ld(rowb + 4u * (uint32_t)(x == 0 ? W - 1 : x - 1));
+                    const uint32_t nxt = lds_ld(rowb + 4u * (uint32_t)(x + 1 == W ? x : x + 1));
+                    const uint32_t dn = lds_ld(lb + (uint32_t)((y + 1 == L ? 0 : y + 1) * W + x) * 4u);
+                    pre = ising_pre(cur, prv, nxt, dn, x == 0, x + 1 == W);
+                }
+                // then the walker must have finished (y-1, w0+B-1) and, for a
+                // row's last batch, (y, 0)
+                const uint32_t g0 = c * (uint32_t)B;   // the batch's first dword since the launch began
+                const uint32_t want = (w0 + B == W) ? g0 - (uint32_t)w0 + 1u : g0 + (uint32_t)(B - W);
+                if (!stream_wait(ctr, kCtrDone, want, l.wait_polls)) {
+                    ok = false;
+                    break;
+                }
+                if (has) {
+                    // the row above as this sweep left it
+                    const uint32_t xu = cur ^ lds_ld(lb + (uint32_t)((y == 0 ? L - 1 : y - 1) * W + x) * 4u);
+                    uint32_t d0 = pre.x + xu, d1 = pre.y + xu;
+                    if (x + 1 == W) {
+                        // right neighbour of the row's last site: the row's first site, this sweep
+                        const uint32_t cr = (cur ^ (lds_ld(rowb) << 24)) & 0xFF000000u;
+                        d0 += cr;
+                        d1 += cr;
+                    }
+                    FastBulk fb;
+                    bulk_cols<false>(BulkDiff{cur, d0, d1}, fb);
+                    bulk_steps<false>(BulkDiff{cur, d0, d1}, fb);
+                    const uint32_t slot = rbp + (uint32_t)x * 32u;
+                    lds_st4(slot, u);
+                    lds_st4(slot + 16u, make_uint4(fb.a0, fb.a1, fb.e0, fb.e1));
+                }
+                // publish in order: after batch c - 1 (formed by the previous wave)
+                if (!stream_wait(ctr, kCtrFormed, c, l.wait_polls)) {
+                    ok = false;
+                    break;
+                }
+                if (lane == 0) lds_st_sync(ctr + kCtrFormed, c + 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && lds_ld_sync(ctr + kCtrAbort)) __hip_atomic_fetch_or(l.status, kStatusWaitExpired, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint32_t v = lds_ld(spin0 + (uint32_t)(c * P + d) * 4u);
+        g_u8 *g = (g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        g[0] = (uint8_t)v;
+        g[p.C] = (uint8_t)(v >> 8);
+        g[2 * (int64_t)p.C] = (uint8_t)(v >> 16);
+        g[3 * (int64_t)p.C] = (uint8_t)(v >> 24);
+    }
+}
+
 // ------------------------------------------------------------------ packed Ising walker
 //
 // At L = 64 a byte per spin is 4 KB per chain: with the 80 KB table only 16
@@ -1330,6 +1702,10 @@ __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const Wo
         case 128: run_ising_packed<128, true>(p, it, lds, l, sweep0, plan); return true;
         default: return false;
         }
+    }
+    if (!MAG && stream_ising(p, it)) {
+        run_ising_stream<64>(p, it, lds, l, sweep0, plan);
+        return true;
     }
     switch (p.L) {
     case 16: run_ising_fast<16, MAG>(p, it, lds, l, sweep0, plan); return true;
