@@ -897,8 +897,8 @@ __device__ __forceinline__ void run_ising_fast(const ProbDev &p, const WorkItem 
 //
 // Walker and producers exchange progress through LDS counters instead of
 // workgroup barriers:
-//   - the walker publishes, after every batch of kStreamBatch dwords, the
-//     number of dwords it has finished;
+//   - the walker publishes the number of dwords it has finished after every
+//     batch of kStreamBatch dwords and after each row's first dword;
 //   - producer wave i forms the batches i, i+np, i+2np, ... of every sweep (np
 //     producer waves); the batches are published in order, on one counter of
 //     the batches formed, each wave waiting for the previous batch's.
@@ -1100,12 +1100,13 @@ __device__ __forceinline__ void run_ising_stream(const ProbDev &p, const WorkIte
                             }
                         };
                         // the previous dword's flips go into the lattice; after a
-                        // batch's last dword, the walker reports the batch done
+                        // batch's last dword, and after a row's first dword (which
+                        // the row's last batch needs), the walker reports its progress
                         auto done = [&](uint32_t fp) {
                             lds_xor(apend, fp);
-                            if (q == 0) {
+                            if (q == 0 || w == 1) {
                                 lds_order();
-                                lds_st_sync(ctr + kCtrDone, c * (uint32_t)B);
+                                lds_st_sync(ctr + kCtrDone, c * (uint32_t)B + (uint32_t)q);
                             }
                         };
                         fpend = walk_dword_stream(st, b, nb, u, fpend, work, done);
