@@ -187,6 +187,9 @@ def main():
                     help="instead of the benchmark: sweep throughput of an L x L lattice versus the number of chains")
     ap.add_argument("--scan-model", default="ising", choices=["ising", "potts8"],
                     help="model of --scan-chains")
+    ap.add_argument("--chains", type=int, default=0,
+                    help="run a single-problem workload with this many chains instead of its own count "
+                         "(a profiling aid; the benchmark line then names the count)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size kernel for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -225,6 +228,12 @@ def main():
         plan = {"ising64": C2, "potts32": C3, "mixed": C4, "mag32": C_MAG}[args.workload]
         probs = list(plan.problems)
         M = plan.sweeps_per_iter
+    if args.chains:
+        if len(probs) != 1:
+            print("--chains applies to single-problem workloads", file=sys.stderr)
+            sys.exit(2)
+        p0 = probs[0]
+        probs = [Problem(p0.model, p0.L, args.chains, p0.seed, q=p0.q, beta=p0.beta)]
     prob = probs[0]
     torch.cuda.set_device(0)
     opts = dict(rng_mode=args.rng_mode, chains_per_wg=args.chains_per_wg, use_graph=int(args.graph))
@@ -287,6 +296,8 @@ def main():
         "ising128": "2D Ising L=128 periodic, 8192 chains, one weight iteration of 2000 sweeps from lnW = 0",
         "potts48": "2D 8-state Potts L=48 periodic, 8192 chains, one weight iteration of 2000 sweeps from lnW = 0",
     }[args.workload]
+    if args.chains:
+        workload_text += f"; run with {args.chains} chains instead"
     # one lane per chain, sequential updates within a chain
     chains = sum(p.n_chains for p in probs)
     bound_ups = chains * CLOCK_HZ / DECISION_CHAIN_CYCLES
