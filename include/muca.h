@@ -107,6 +107,13 @@ typedef struct {
  *                    reachable bins inward (or the far edge if the region is
  *                    narrower), likewise above k_hi (the correction function
  *                    of Sec. 3)
+ *   update_norm      1 = the recursion's update over the visited bins is
+ *                    shifted to zero mean: lnW(k) -= ln H(k) - <ln H> for
+ *                    H(k) > 0, <ln H> the mean over those bins (a reading of
+ *                    Sec. 2: dividing W by H fixes W only up to one constant
+ *                    per iteration, since H may be normalized in any way; this
+ *                    chooses the constant that keeps the visited region's mean
+ *                    weight against the unvisited bins).  0 = raw counts
  *   wait_polls       polls of the bounded waits between a streamed walker
  *                    and its helper waves before they give up (0 = default,
  *                    2^24, a second or more; negative = none, so that every
@@ -125,6 +132,8 @@ typedef struct {
     int32_t tune_sweeps;
     int32_t correction;
     int32_t wait_polls;
+    int32_t update_norm;
+    int32_t pad;
 } muca_options;
 
 /* Statistics of one weight iteration for one problem, from the merged

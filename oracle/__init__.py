@@ -56,10 +56,11 @@ def lib():
                                  i32p, i32p, i32p, i64p, c_int]
         L.orc_merge.argtypes = [c_int, c_int, i32p, i64p]
         L.orc_recursion.argtypes = [c_int, i64p, f64p]
+        L.orc_recursion_norm.argtypes = [c_int, i64p, f64p]
         for f in ("orc_philox4x32_10", "orc_energy", "orc_reachable", "orc_bruteforce",
                   "orc_bruteforce_canonical", "orc_init", "orc_build_table", "orc_build_table_mag",
                   "orc_bruteforce_mag", "orc_sweeps",
-                  "orc_merge", "orc_recursion"):
+                  "orc_merge", "orc_recursion", "orc_recursion_norm"):
             getattr(L, f).restype = None
         _lib = L
     return _lib
@@ -222,16 +223,18 @@ class OracleRun:
         lib().orc_merge(self.n_chains, self.n_bins, self.hist, H)
         return H
 
-    def iterate(self, n_sweeps: int, ratio: float = 0.5, rule: int = 0, correct: bool = False):
+    def iterate(self, n_sweeps: int, ratio: float = 0.5, rule: int = 0, correct: bool = False,
+                norm: bool = False):
         """One weight iteration: sweeps with histograms, merge, flatness on
-        the merged histogram, recursion (optionally followed by the
-        correction function), new table, cleared histograms."""
+        the merged histogram, recursion (with norm, its update shifted to zero
+        mean over the visited bins; optionally followed by the correction
+        function), new table, cleared histograms."""
         self.hist[:] = 0
         self.sweeps(n_sweeps, REC_MUCA)
         H = self.merged()
         fl = flatness(H, self.mask, ratio, rule)
         per_chain = self.hist.copy()
-        lib().orc_recursion(self.n_bins, H, self.lnW)
+        (lib().orc_recursion_norm if norm else lib().orc_recursion)(self.n_bins, H, self.lnW)
         if correct:
             correction(self.lnW, H, self.mask, self.L)
         self.T = self._table()

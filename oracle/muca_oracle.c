@@ -455,3 +455,21 @@ void orc_recursion(int n_bins, const int64_t *H, double *lnW)
     for (int b = 0; b < n_bins; ++b)
         if (H[b] > 0) lnW[b] -= log((double)H[b]);
 }
+
+/* The same recursion with the update over the visited bins shifted to zero
+ * mean (a reading of Sec. 2: W / H fixes W only up to one constant per
+ * iteration): ln H(b) minus its mean over the bins with H(b) > 0, the mean
+ * summed in bin order. */
+void orc_recursion_norm(int n_bins, const int64_t *H, double *lnW)
+{
+    double sum = 0.0;
+    int n = 0;
+    for (int b = 0; b < n_bins; ++b)
+        if (H[b] > 0) {
+            sum += log((double)H[b]);
+            ++n;
+        }
+    const double mean = n > 0 ? sum / n : 0.0;
+    for (int b = 0; b < n_bins; ++b)
+        if (H[b] > 0) lnW[b] -= log((double)H[b]) - mean;
+}

@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("spin_placement", ctypes.c_int32), ("table_placement", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("production", ctypes.c_int32),
                 ("flat_ratio", ctypes.c_double), ("flat_rule", ctypes.c_int32),
-                ("tune_sweeps", ctypes.c_int32), ("correction", ctypes.c_int32), ("wait_polls", ctypes.c_int32)]
+                ("tune_sweeps", ctypes.c_int32), ("correction", ctypes.c_int32), ("wait_polls", ctypes.c_int32),
+                ("update_norm", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class IterStats(ctypes.Structure):

@@ -159,6 +159,7 @@ muca_status validate(const muca_problem *pr, int32_t n, const muca_options *o) {
             return fail(nullptr, MUCA_EINVAL, "placements must be 0..2");
         if (o->flat_rule < 0 || o->flat_rule > 1) return fail(nullptr, MUCA_EINVAL, "flat_rule must be 0 or 1");
         if (o->correction < 0 || o->correction > 1) return fail(nullptr, MUCA_EINVAL, "correction must be 0 or 1");
+        if (o->update_norm < 0 || o->update_norm > 1) return fail(nullptr, MUCA_EINVAL, "update_norm must be 0 or 1");
     }
     return MUCA_OK;
 }
@@ -268,9 +269,23 @@ void stats_of(const ProbHost &p, const int64_t *H, double ratio, int rule, muca_
     s.flat = flat;
 }
 
-void recursion(ProbHost &p, const int64_t *H) {
+void recursion(ProbHost &p, const int64_t *H, int update_norm) {
+    if (!update_norm) {
+        for (int k = 0; k < p.nbins; ++k)
+            if (H[k] > 0) p.lnW[k] -= std::log((double)H[k]);
+        return;
+    }
+    // the update shifted to zero mean over the visited bins
+    double sum = 0.0;
+    int n = 0;
     for (int k = 0; k < p.nbins; ++k)
-        if (H[k] > 0) p.lnW[k] -= std::log((double)H[k]);
+        if (H[k] > 0) {
+            sum += std::log((double)H[k]);
+            ++n;
+        }
+    const double mean = n > 0 ? sum / n : 0.0;
+    for (int k = 0; k < p.nbins; ++k)
+        if (H[k] > 0) p.lnW[k] -= std::log((double)H[k]) - mean;
 }
 
 // Correction function (Sec. 3): beyond each edge of the sampled region,
@@ -633,7 +648,7 @@ void host_update(muca_ctx ctx, int update) {
         const int64_t *H = ctx->pin_H + p.off_H;
         stats_of(p, H, ctx->opt.flat_ratio, ctx->opt.flat_rule, p.last);
         if (update) {
-            recursion(p, H);
+            recursion(p, H, ctx->opt.update_norm);
             if (ctx->opt.correction) correction(p, H);
             device_table(p, ctx->pin_tab + p.tab_stage_off);
         }

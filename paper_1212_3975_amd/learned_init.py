@@ -111,7 +111,8 @@ def test(params_path: str, out_dir: str, sizes, chains: int, sweeps: int, cap_pl
                 # arms: "plain" / "learned" start from lnW = 0 / the prediction; a
                 # "+corr" suffix turns on the correction function of the recursion
                 base, _, extra = arm.partition("+")
-                with pm.Muca([prob], correction=int(extra == "corr")) as ctx:
+                mods = set(extra.split("+")) if extra else set()
+                with pm.Muca([prob], correction=int("corr" in mods), update_norm=int("norm" in mods)) as ctx:
                     if base == "learned":
                         mlp.set_log_weights(ctx, 0)
                     cap = cap_learned if base == "learned" else cap_plain

@@ -254,6 +254,27 @@ def test_correction_function_bit_exact(prob):
             assert np.array_equal(ctx.spins(), orc.spins)
 
 
+@pytest.mark.parametrize("prob,correct", [(Problem(ISING, 16, 48, 61), False), (Problem(POTTS, 8, 40, 62, q=8), False),
+                                          (Problem(ISING, 12, 32, 63), True)],
+                         ids=["ising16", "potts8", "ising12-corr"])
+def test_normalized_update_bit_exact(prob, correct):
+    """The recursion with its update shifted to zero mean over the visited
+    bins (update_norm = 1), alone and followed by the correction function:
+    weights as bits, histograms and trajectories equal the oracle's over six
+    iterations, through mucaIterate."""
+    pm = _pm()
+    with pm.Muca([prob], update_norm=1, correction=int(correct)) as ctx:
+        orc = _orc(prob)
+        for it in range(6):
+            print(f"  iteration {it}", flush=True)
+            ctx.iterate(150)
+            H, _, _ = orc.iterate(150, correct=correct, norm=True)
+            assert np.array_equal(ctx.H(), H)
+            assert _same_bits(ctx.lnW(), orc.lnW), f"lnW differs at iteration {it}"
+            assert np.array_equal(ctx.table(), device_table(orc))
+            assert np.array_equal(ctx.spins(), orc.spins)
+
+
 @pytest.mark.parametrize("rule,ratio,want", [(1, 0.5, [0] * 7 + [1] * 5), (0, 0.3, [0] * 6 + [1] * 6),
                                               (0, 0.75, [0] * 9 + [1, 1, 0])],
                          ids=["paper-rule", "ratio0.3", "ratio0.75"])

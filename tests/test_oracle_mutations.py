@@ -24,6 +24,12 @@ MUTATIONS = [
      "r = (k % 2 == 0) && k != 2;", "test_oracle_pins.py", "beale_invariants"),
     ("recursion-sign", "muca_oracle.c", "if (H[b] > 0) lnW[b] -= log((double)H[b]);",
      "if (H[b] > 0) lnW[b] += log((double)H[b]);", "test_oracle_pins.py", "converges_to_exact_dos_ising_L4"),
+    ("norm-sum-not-mean", "muca_oracle.c", "const double mean = n > 0 ? sum / n : 0.0;",
+     "const double mean = n > 0 ? sum : 0.0;", "test_oracle_pins.py", "normalized"),
+    ("norm-mean-over-all-bins", "muca_oracle.c", "const double mean = n > 0 ? sum / n : 0.0;",
+     "const double mean = n > 0 ? sum / n_bins : 0.0;", "test_oracle_pins.py", "normalized"),
+    ("norm-shift-sign", "muca_oracle.c", "if (H[b] > 0) lnW[b] -= log((double)H[b]) - mean;",
+     "if (H[b] > 0) lnW[b] -= log((double)H[b]) + mean;", "test_oracle_pins.py", "normalized"),
     ("correction-slope", "__init__.py", "slope = (lnW[lo] - lnW[a]) / float(lo - a)",
      "slope = (lnW[lo] - lnW[a]) / float(a - lo)", "test_oracle_pins.py", "correction"),
     ("dk-sign", "muca_oracle.c", "int dk = after - before;", "int dk = before - after;",

@@ -389,6 +389,54 @@ def test_small_ising_run_reaches_exact_dos_L8():
     assert np.abs(d).max() < 0.35 and d.std() < 0.1
 
 
+def _norm_update(H, lnW):
+    out = np.array(lnW, np.float64)
+    oracle.lib().orc_recursion_norm(H.size, np.ascontiguousarray(H, np.int64), out)
+    return out
+
+
+def test_normalized_recursion_hand_example():
+    """The update shifted to zero mean over the visited bins (a reading of
+    Sec. 2 that fixes W / H's free constant), worked by hand: H = (0, 4, 1, 16)
+    has ln H = (ln 4, 0, ln 16) on its visited bins, mean ln 4, so the weights
+    move by (0, 0, +ln 4, -ln 4)."""
+    H = np.array([0, 4, 1, 16], np.int64)
+    got = _norm_update(H, [0.5, 0.0, 0.0, 0.0])
+    assert got == pytest.approx([0.5, 0.0, math.log(4), -math.log(4)], abs=1e-15)
+    # the plain recursion on the same counts: (0.5, -ln 4, 0, -ln 16)
+    plain = np.array([0.5, 0.0, 0.0, 0.0])
+    oracle.lib().orc_recursion(4, H, plain)
+    assert plain == pytest.approx([0.5, -math.log(4), 0.0, -math.log(16)], abs=1e-15)
+
+
+def test_normalized_recursion_properties():
+    """Unvisited bins keep their weights; over the visited bins the change
+    has zero mean and differs from the plain recursion's by one constant; the
+    result does not depend on how the histogram is normalized (H and 64 H give
+    the same weights), which the plain recursion's does; a flat histogram
+    leaves the weights unchanged."""
+    rng = np.random.default_rng(5)
+    n = 301
+    H = rng.integers(1, 5000, n).astype(np.int64)
+    H[rng.random(n) < 0.3] = 0
+    lnW = rng.normal(0, 3, n)
+    got = _norm_update(H, lnW)
+    vis = H > 0
+    assert np.array_equal(got[~vis], lnW[~vis])
+    delta = got[vis] - lnW[vis]
+    assert abs(delta.mean()) < 1e-12
+    plain = lnW.copy()
+    oracle.lib().orc_recursion(n, H, plain)
+    shift = (got - plain)[vis]
+    assert np.ptp(shift) < 1e-12 and shift[0] == pytest.approx(np.log(H[vis]).mean(), rel=1e-12)
+    assert _norm_update(64 * H, lnW) == pytest.approx(got, abs=1e-12)
+    plain64 = lnW.copy()
+    oracle.lib().orc_recursion(n, 64 * H, plain64)
+    assert not np.allclose(plain64[vis], plain[vis])
+    flat = np.where(vis, 777, 0).astype(np.int64)
+    assert _norm_update(flat, lnW) == pytest.approx(lnW, abs=1e-12)
+
+
 def test_correction_function_properties():
     """The correction function (Sec. 3) leaves the sampled region alone, puts
     every reachable bin outside it on the line through the edge bin and the
