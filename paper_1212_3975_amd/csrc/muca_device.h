@@ -73,7 +73,8 @@ int lds_bytes_for(const ProbDev &p, const WorkItem &it, int n_producer_waves);
 // Chunks per sweep of the walker that runs this work item; a launch of S
 // sweeps counts S times this many chunks in an int32.
 int chunks_per_sweep(const ProbDev &p, const WorkItem &it, int n_producer_waves);
-// Whether the sweep kernel takes the fast Ising walker for this problem.
+// Whether the sweep kernel takes one of the fast walkers (four sites per step:
+// Ising, multimagnetic or 8-Potts) for this problem.
 bool uses_fast_walker(const ProbDev &p, int n_producer_waves);
 // The walker that runs a work item (the codes of muca_launch_info.walker).
 int walker_kind(const ProbDev &p, const WorkItem &it, int n_producer_waves);
