@@ -1143,7 +1143,8 @@ __device__ __forceinline__ void run_ising_stream(const ProbDev &p, const WorkIte
         }
     } else {
         // producer wave i: batch bb of every sweep with bb = i mod np; lane r
-        // forms the record of chain r / B, dword r mod B of the batch
+        // forms the record of chain r / B, dword r mod B of the batch (a wave's
+        // 64 lanes cover a batch: stream_ising admits at most 16 chains)
         const int i = wave - 1;
         const int r = lane;
         const bool has = r < nch * B;
