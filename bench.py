@@ -161,6 +161,7 @@ def scan_chains(L, pm, torch, Problem, model):
         rows.append({"chains": chains, "sweeps": sweeps, "kernel_ms": round(ms, 3), "Gups": round(rate / 1e9, 2),
                      "alu_frac": round(ops * rate / PEAK_INT32_OPS, 4),
                      "chains_per_wg": info["chains_per_wg"], "fast_walker": info["fast_walker"],
+                     "walker": info["walker"],
                      "workgroups": info["n_workgroups"]})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     name = f"2D 8-state Potts L={L}" if potts else f"2D Ising L={L}"
