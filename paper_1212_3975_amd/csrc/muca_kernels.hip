@@ -1161,7 +1161,11 @@ __device__ __forceinline__ void run_ising_stream(const ProbDev &p, const WorkIte
                 // everything that does not depend on the walker first: the random
                 // words, and the counts over the old left, right and lower
                 // neighbours (the right neighbour of a row's last site, the row's
-                // first site of this sweep, excepted)
+                // first site of this sweep, excepted).  These dwords hold their
+                // previous sweep's final values: the walker updates them only after
+                // this batch is published, and it finished their previous sweep
+                // (and, below the last row, row 0 of this sweep) long before this
+                // wave's previous batch could be formed.
                 const uint32_t rowb = lb + (uint32_t)(y * W) * 4u;
                 uint4 u = make_uint4(0, 0, 0, 0);
                 uint32_t cur = 0;
