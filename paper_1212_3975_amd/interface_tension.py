@@ -50,7 +50,8 @@ def rescaled_weights(lnW_prev, L_prev, L):
     return N * np.interp(e_new, e_prev, np.asarray(lnW_prev, np.float64) / Np)
 
 
-def run_size(L, chains, seed, sweeps, cap, refine, n_therm, n_prod, mlp, max_seconds, seed_lnw=None, flat_rule=0):
+def run_size(L, chains, seed, sweeps, cap, refine, n_therm, n_prod, mlp, max_seconds, seed_lnw=None, flat_rule=0,
+             iterate=True, blocks=0):
     prob = Problem(POTTS, L, chains, seed, q=8)
     rec = {"L": L, "chains": chains, "seed": seed, "sweeps_per_iter": sweeps,
            "weights_seed": "given" if seed_lnw is not None else ("learned" if mlp is not None else "zero")}
@@ -61,13 +62,16 @@ def run_size(L, chains, seed, sweeps, cap, refine, n_therm, n_prod, mlp, max_sec
             ctx.set_log_weights(0, seed_lnw)
         elif mlp is not None:
             mlp.set_log_weights(ctx, 0)
-        n_flat, _ = iterate_to_flat(ctx, sweeps, cap, f"potts8 L={L}", log_every=10, max_seconds=max_seconds)
-        rec["iterations_to_flat"] = n_flat
-        if n_flat is None:
-            rec["seconds"] = round(time.time() - t0, 1)
-            return rec, None, None
-        for _ in range(refine):
-            ctx.iterate(sweeps)
+        if iterate:
+            n_flat, _ = iterate_to_flat(ctx, sweeps, cap, f"potts8 L={L}", log_every=10, max_seconds=max_seconds)
+            rec["iterations_to_flat"] = n_flat
+            if n_flat is None:
+                rec["seconds"] = round(time.time() - t0, 1)
+                return rec, None, None
+            for _ in range(refine):
+                ctx.iterate(sweeps)
+        else:
+            rec["iterations_to_flat"] = 0   # production on the given weights as they are
         lnW = ctx.lnW(0)
         ctx.sweep(n_therm, pm.REC_NONE)
         done = 0
@@ -91,6 +95,22 @@ def run_size(L, chains, seed, sweeps, cap, refine, n_therm, n_prod, mlp, max_sec
             return rec, None, lnW
         rec.update(beta_eqh=res["beta"], sigma_od=res["sigma"], k_peaks=list(res["k_peaks"]),
                    ln_ratio=res["sigma"] * 2 * L)
+        if blocks:
+            # the same analysis on disjoint blocks of chains (each block's merged
+            # production counts, the run's weights): how much of the spread of
+            # sigma between runs the chains of one run already show
+            per_chain = ctx.chain_hist(0).astype(np.int64)
+            size = chains // blocks
+            rec["blocks"] = []
+            for b in range(blocks):
+                cnt = per_chain[b * size:(b + 1) * size].sum(axis=0)
+                try:
+                    rb = pm.equal_height(POTTS, L, lnW, cnt, BETA0 - rec["bracket_half_width"],
+                                         BETA0 + rec["bracket_half_width"])
+                    rec["blocks"].append({"beta_eqh": rb["beta"], "sigma_od": rb["sigma"],
+                                          "k_peaks": list(rb["k_peaks"]), "ln_ratio": rb["sigma"] * 2 * L})
+                except pm.MucaError as e:
+                    rec["blocks"].append({"error": str(e)})
         return rec, res["lnP"], lnW
 
 
@@ -116,6 +136,9 @@ def main():
                     help="seed each size after the first with the previous size's weights, rescaled per site")
     ap.add_argument("--fit-min-l", type=int, default=16, help="smallest L in the 1/L fit")
     ap.add_argument("--max-seconds", type=float, default=600.0, help="wall-time limit of one size's iteration")
+    ap.add_argument("--no-iterate", action="store_true",
+                    help="with --weights: production on the given weights without iterating them first")
+    ap.add_argument("--blocks", type=int, default=0, help="also analyse this many disjoint blocks of chains")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -140,7 +163,8 @@ def main():
         if own is not None and f"L{L}" in own.files:
             seed_lnw = np.asarray(own[f"L{L}"], np.float64)
         rec, lnP, lnW = run_size(L, args.chains, args.seed, args.sweeps, args.cap, args.refine, args.therm,
-                                 args.prod, mlp, args.max_seconds, seed_lnw, args.flat_rule)
+                                 args.prod, mlp, args.max_seconds, seed_lnw, args.flat_rule,
+                                 iterate=not (args.no_iterate and seed_lnw is not None), blocks=args.blocks)
         results.append(rec)
         if lnP is not None:
             hists[f"L{L}"] = lnP
