@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--rng-mode", type=int, default=0)
     ap.add_argument("--chains-per-wg", type=int, default=0)
     ap.add_argument("--fixed", action="store_true",
-                    help="skip tuning: 3 producer waves, LDS placement, --chains-per-wg chains per workgroup "
+                    help="skip tuning: 4 helper waves, LDS placement, --chains-per-wg chains per workgroup "
                          "(default 16)")
     ap.add_argument("--no-extra", action="store_true", help="skip the production and reweighting leg")
     ap.add_argument("--workload", default="ising64",
@@ -239,7 +239,7 @@ def main():
     torch.cuda.set_device(0)
     opts = dict(rng_mode=args.rng_mode, chains_per_wg=args.chains_per_wg, use_graph=int(args.graph))
     if args.fixed:
-        opts.update(rng_mode=4, chains_per_wg=args.chains_per_wg or 16, spin_placement=1, table_placement=1)
+        opts.update(rng_mode=5, chains_per_wg=args.chains_per_wg or 16, spin_placement=1, table_placement=1)
     ctx = pm.Muca(probs, device="cuda:0", **opts)
     launch = [ctx.launch_info(i) for i in range(len(probs))]
     updates_per_step = sum(p.n_chains * p.N for p in probs) * M

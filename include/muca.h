@@ -89,7 +89,7 @@ typedef struct {
  *                    table both fit in LDS); a count whose arrays do not fit
  *                    in the requested placement makes mucaInit fail
  *   rng_mode         0 = tune, 1 = walker draws its own numbers,
- *                    2, 3, 4 = one, two or three helper waves of the
+ *                    2, 3, 4, 5 = one, two, three or four helper waves of the
  *                    workgroup draw them (and, for the fast walkers, form
  *                    the lattice terms the walker's updates cannot change)
  *   spin_placement   0 = tune, 1 = lattice in LDS, 2 = lattice in HBM

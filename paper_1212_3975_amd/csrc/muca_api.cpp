@@ -154,7 +154,8 @@ muca_status validate(const muca_problem *pr, int32_t n, const muca_options *o) {
     if (o) {
         const int cw = o->chains_per_wg;
         if (cw < 0 || cw > 64) return fail(nullptr, MUCA_EINVAL, "chains_per_wg must be 0 (tune) or 1..64");
-        if (o->rng_mode < 0 || o->rng_mode > 4) return fail(nullptr, MUCA_EINVAL, "rng_mode must be 0..4");
+        if (o->rng_mode < 0 || o->rng_mode > 1 + kMaxProducerWaves)
+            return fail(nullptr, MUCA_EINVAL, "rng_mode must be 0..%d", 1 + kMaxProducerWaves);
         if (o->spin_placement < 0 || o->spin_placement > 2 || o->table_placement < 0 || o->table_placement > 2)
             return fail(nullptr, MUCA_EINVAL, "placements must be 0..2");
         if (o->flat_rule < 0 || o->flat_rule > 1) return fail(nullptr, MUCA_EINVAL, "flat_rule must be 0 or 1");
@@ -542,9 +543,9 @@ muca_status configure(muca_ctx ctx) {
     const muca_options &o = ctx->opt;
     // rng candidates: own (0 producers) or 1..3 producer waves
     std::vector<int> rng_cands;
-    if (o.rng_mode == 0) rng_cands = {0, 1, 2, 3};
+    if (o.rng_mode == 0) rng_cands = {0, 1, 2, 3, 4};
     else if (o.rng_mode == 1) rng_cands = {0};
-    else rng_cands = {std::min(3, std::max(1, o.rng_mode - 1))};
+    else rng_cands = {std::min(kMaxProducerWaves, std::max(1, o.rng_mode - 1))};
     std::vector<int> cw_cands;
     if (o.chains_per_wg) cw_cands = {o.chains_per_wg};
     else cw_cands = {16, 32, 64};

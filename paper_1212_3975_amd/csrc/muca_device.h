@@ -15,7 +15,7 @@ constexpr int kRecProd = 2;
 // Sites whose random words one producer pass stages in LDS per chain.
 constexpr int kChunkSites = 64;
 constexpr int kMaxChainsPerWG = 64;
-constexpr int kMaxProducerWaves = 3;
+constexpr int kMaxProducerWaves = 4;
 
 // Device view of one problem.  Spins are site-major with the chain index
 // fastest ([N][C]) so that the chains of a workgroup read consecutive bytes.

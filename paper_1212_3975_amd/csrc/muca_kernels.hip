@@ -2247,7 +2247,7 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     }
 }
 
-__global__ void __launch_bounds__(256) sweep_kernel(SweepLaunch l) {
+__global__ void __launch_bounds__(64 * (1 + kMaxProducerWaves)) sweep_kernel(SweepLaunch l) {
     extern __shared__ __align__(16) char lds[];
     const WorkItem it = l.items[blockIdx.x];
     const ProbDev p = l.probs[it.prob];

@@ -430,7 +430,7 @@ def test_packed_l64_walker_bit_exact(chains, cw):
         assert np.array_equal(ctx.spins(), orc.spins)
 
 
-@pytest.mark.parametrize("rng_mode", [2, 4], ids=["one-producer", "three-producers"])
+@pytest.mark.parametrize("rng_mode", [2, 4, 5], ids=["one-producer", "three-producers", "four-producers"])
 @pytest.mark.parametrize("prob,n_sweeps,cw", [(Problem(ISING, 16, 40, 51), 3000, 16),
                                               (Problem(POTTS, 16, 40, 52, q=8), 3000, 16),
                                               (Problem(ISING_MAG, 16, 40, 53, beta=0.66), 3000, 16),

@@ -3,7 +3,7 @@ workgroup, the benchmark's launch) against the oracle, through the C ABI.
 
 Its helper waves form every dword's complete bulk from the row above as the
 walker leaves it, and the two sides hand records and progress over through LDS
-counters instead of barriers.  The cases cover one, two and three helper waves,
+counters instead of barriers.  The cases cover one to four helper waves,
 workgroups that are partly empty, chains split over several work items,
 launches of a single sweep (the hand-over at launch start and end), production
 (|M| with the last dword's flips still pending), and chains at both ends of the
@@ -34,9 +34,9 @@ def _compare_state(ctx, orc):
 
 
 @pytest.mark.parametrize("chains,cw,rng_mode", [(1, 16, 2), (7, 16, 3), (16, 16, 4), (20, 16, 4), (37, 12, 2),
-                                                (16, 16, 2)],
+                                                (16, 16, 2), (16, 16, 5), (23, 12, 5)],
                          ids=["c1-one-helper", "c7-two-helpers", "c16-three-helpers", "c20-two-items",
-                              "c37-cw12-one-helper", "c16-one-helper"])
+                              "c37-cw12-one-helper", "c16-one-helper", "c16-four-helpers", "c23-cw12-four-helpers"])
 def test_streamed_walker_iterations_bit_exact(chains, cw, rng_mode):
     """Two weight iterations with the correction function (real weights from
     the second on), then one launch of 400 sweeps: per-chain and merged
