@@ -93,7 +93,7 @@ __host__ __device__ inline int round_up(int v, int a) { return (v + a - 1) / a *
 struct LdsPlan {
     int off_tab, off_spin, off_ring, total;
     int off_rows;   // packed Ising walker only: the ring of unpacked rows
-    int off_ctr;    // streamed Ising walker only: progress counters
+    int off_ctr;    // streamed walkers only: progress counters
 };
 // The packed Ising walker: L = 64 with more than 16 chains per workgroup
 // (32-bit table), and L = 96 and 128 with the compact table below.  A lane's
@@ -145,6 +145,14 @@ __host__ __device__ constexpr int stream_lane_words(int L) { return (L / 4) * 8 
 __host__ __device__ inline bool stream_ising(const ProbDev &p, const WorkItem &it) {
     return p.model == kIsing && p.L == 64 && it.nchains <= 16;
 }
+// The streamed compact Potts walker (run_potts_stream): 8-Potts L = 48 with up
+// to 32 chains per workgroup; per lane a ring of one row of 48-byte records and
+// a 16-byte pad.
+constexpr int kPStreamBatch = 4;   // dwords per producer batch and progress report
+__host__ __device__ constexpr int pstream_lane_words(int L) { return (L / 4) * 12 + 4; }
+__host__ __device__ inline bool stream_potts(const ProbDev &p, const WorkItem &it) {
+    return compact_potts(p) && it.nchains <= 32;
+}
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
     l.off_tab = 0;
@@ -178,6 +186,13 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
         const int cdw = fast_rows_per_chunk(p.L) * W;
         l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
         l.total = l.off_ring + 2 * it.nchains * (cdw + 1) * 24;
+        return l;
+    }
+    if (fast_potts_ok(p, n_producer_waves) && stream_potts(p, it)) {
+        // lane-major lattice with an odd dword stride; record rings; counters
+        l.off_ring = l.off_spin + round_up(it.nchains * fast_lane_stride(p.L) * 4, 16);
+        l.off_ctr = l.off_ring + it.nchains * pstream_lane_words(p.L) * 4;
+        l.total = l.off_ctr + 4 * kStreamCtrWords;
         return l;
     }
     if (fast_potts_ok(p, n_producer_waves)) {
@@ -237,7 +252,7 @@ int walker_kind(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
         if (p.model == kIsing && stream_ising(p, it)) return 6;
         return 1;
     }
-    if (fast_potts_ok(p, n_producer_waves)) return compact_potts(p) ? 5 : 4;
+    if (fast_potts_ok(p, n_producer_waves)) return stream_potts(p, it) ? 7 : compact_potts(p) ? 5 : 4;
     return 0;
 }
 
@@ -1406,6 +1421,15 @@ __device__ __noinline__ RedoResult redo_compact_dword(uint32_t R, uint32_t C, ui
 // draws.  If any site of the dword drew a == t, the whole dword is recomputed
 // exactly from the state at its start (redo_compact_dword; ex holds the
 // table, the Philox block of the dword and the generator's key).
+// r + byte 0 of codes in one SDWA instruction (the compiler otherwise masks the
+// byte with a separate instruction when the word also feeds other uses).
+__device__ __forceinline__ uint32_t add_byte0(uint32_t r, uint32_t codes) {
+    uint32_t d;
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(d) : "v"(r), "v"(codes));
+    return d;
+}
+
 struct CompactExact {
     uint32_t tab0;
     const uint32_t *table;
@@ -1414,9 +1438,9 @@ struct CompactExact {
 
 __device__ __forceinline__ RedoResult compact_redo(uint32_t R0, uint32_t C0, bool acc0, const CompactBulk &b,
                                                    const CompactBulk &nb, const uint4 &u, const CompactExact &ex) {
-    return redo_compact_dword(R0, C0, acc0 ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1, ubyte(nb.a0, 0),
-                              ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain,
-                              ex.seed_lo, ex.seed_hi);
+    return redo_compact_dword(R0, C0, acc0 ? 1u : 0u, b.a0, b.a1, b.e0, b.e1, b.z0, b.z1,
+                              __builtin_amdgcn_ubfe(nb.a0, 0u, 8u), __builtin_amdgcn_ubfe(nb.a1, 0u, 8u), u.x, u.y,
+                              u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain, ex.seed_lo, ex.seed_hi);
 }
 
 template <class Bulk, uint32_t FLIP, int STRIDE, class Work>
@@ -1424,23 +1448,32 @@ __device__ __forceinline__ uint32_t walk_dword_compact(CompactState &s, const Bu
                                                        Work &&work, const CompactExact &ex) {
     const uint32_t R0 = s.R, C0 = s.C;   // the state at the dword's start, for an exact redo
     const bool acc0 = s.acc != 0u;
+    bool acc = acc0;                     // the previous site's outcome, as a lane mask
     uint32_t f = 0;
     bool tie = false;
+    bool eq = false;   // the previous site's tie, folded in a site later (its compare has long finished)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const uint32_t Rj = s.acc ? s.C : s.R;
-        const uint32_t Cj = Rj + (uint32_t)row_step(b, s.acc, j);
-        const uint32_t a0 = (j < 3) ? ubyte(b.a0, j + 1) : ubyte(nb.a0, 0);
-        const uint32_t a1 = (j < 3) ? ubyte(b.a1, j + 1) : ubyte(nb.a1, 0);
-        const uint32_t nA = lds_ld16(Rj + a0);
-        const uint32_t nB = lds_ld16(Cj + a1);
+        const uint32_t Rj = acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)row_step(b, acc, j);
+        uint32_t adA, adB;
+        if (j < 3) {
+            adA = Rj + ubyte(b.a0, j + 1);
+            adB = Cj + ubyte(b.a1, j + 1);
+        } else {
+            adA = add_byte0(Rj, nb.a0);
+            adB = add_byte0(Cj, nb.a1);
+        }
+        const uint32_t nA = lds_ld16(adA);
+        const uint32_t nB = lds_ld16(adB);
         __builtin_amdgcn_sched_barrier(0);
         const uint32_t tA = xor_byte1(s.tA, b.z0, j);
         const uint32_t tB = xor_byte1(s.tB, b.z1, j);
-        const uint32_t tj = s.acc ? tB : tA;
+        tie |= eq;
+        const uint32_t tj = acc ? tB : tA;
         const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
-        s.acc = uj < tj;
-        tie |= uj == tj;
+        acc = uj < tj;
+        eq = uj == tj;
         s.R = Rj;
         s.C = Cj;
         s.tA = nA;
@@ -1448,12 +1481,15 @@ __device__ __forceinline__ uint32_t walk_dword_compact(CompactState &s, const Bu
         __builtin_amdgcn_sched_barrier(0);
         work(j);
         __builtin_amdgcn_sched_barrier(0);
-        f |= s.acc ? (FLIP << (STRIDE * j)) : 0u;
+        f |= acc ? (FLIP << (STRIDE * j)) : 0u;
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (tie) {
-        // the exact redo writes the flip record in the walker's format
-        // (FLIP << STRIDE j for an accepted site j)
+    tie |= eq;
+    s.acc = acc ? 1u : 0u;
+    if (__builtin_amdgcn_ballot_w64(tie) != 0u) {
+        // rare: the whole wave redoes the dword exactly (the redo agrees with
+        // the fast path wherever the prefixes decide) and writes the flip
+        // record in the walker's format (FLIP << STRIDE j for an accepted site j)
         const RedoResult r = compact_redo(R0, C0, acc0, b, nb, u, ex);
         s.R = r.s0;
         s.C = r.s1;
@@ -1901,9 +1937,9 @@ __device__ __noinline__ RedoResult redo_compact_potts(uint32_t R, uint32_t C, ui
 
 __device__ __forceinline__ RedoResult compact_redo(uint32_t R0, uint32_t C0, bool acc0, const CompactPottsBulk &b,
                                                    const CompactPottsBulk &nb, const uint4 &u, const CompactExact &ex) {
-    return redo_compact_potts(R0, C0, acc0 ? 1u : 0u, b.a0, b.a1, b.k0, b.k1, b.z0, b.z1, ubyte(nb.a0, 0),
-                              ubyte(nb.a1, 0), u.x, u.y, u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain,
-                              ex.seed_lo, ex.seed_hi);
+    return redo_compact_potts(R0, C0, acc0 ? 1u : 0u, b.a0, b.a1, b.k0, b.k1, b.z0, b.z1,
+                              __builtin_amdgcn_ubfe(nb.a0, 0u, 8u), __builtin_amdgcn_ubfe(nb.a1, 0u, 8u), u.x, u.y,
+                              u.z, u.w, ex.tab0, ex.table, ex.blk, ex.sweep, ex.chain, ex.seed_lo, ex.seed_hi);
 }
 
 template <int L, bool WIDE, bool COMPACT>
@@ -2129,6 +2165,345 @@ __device__ __forceinline__ void run_potts_fast(const ProbDev &p, const WorkItem 
     }
 }
 
+// ------------------------------------------------------------------ streamed compact Potts walker
+//
+// The fast Potts walker at L = 48 forms part of every dword's bulk itself
+// (the terms of the row above, the first site's left proposal, the right
+// neighbour of a row's last site) and decodes the compact table on top: about
+// 150 cycles per site.  As for the streamed Ising walker, the producer waves
+// here form each dword's complete record after the walker has left the row
+// above, and the walker only decides sites.  A record holds:
+//   - the four draws' 14-bit prefixes (the compact comparison);
+//   - the column codes, row steps (8 dk bytes, the compact row stride) and
+//     decode codes of both candidates of every site;
+//   - the xor of the old states and the proposals, which the walker applies
+//     to the accepted sites.
+// The proposal of a dword's last site, which the next dword's first site sees
+// as its left neighbour when it is accepted, is drawn again by the producer of
+// that next dword (one more Philox block), so records never wait for each
+// other.  Progress counters, in-order publishing, bounded waits and the
+// abort path are those of the streamed Ising walker.  A dword with a draw
+// equal to its decoded entry is redone exactly (redo_compact_potts).
+
+// The four sites of one dword: as walk_dword_stream, with the compact decode
+// and the detection of undecidable draws (tie).  The flip record holds 0xff
+// in byte j for an accepted site j.
+template <class Work, class Done>
+__device__ __forceinline__ uint32_t walk_dword_pstream(FastState &s, const uint4 &m, const uint4 &z,
+                                                       const uint4 &nm, const uint4 &u, uint32_t fprev, bool &tie,
+                                                       Work &&work, Done &&done) {
+    uint32_t f = 0;
+    bool eq = false;   // the previous site's tie, folded in a site later (its compare has long finished)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool acc = s.acc;
+        const uint32_t Rj = acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)(acc ? sbyte(m.w, j) : sbyte(m.z, j));
+        uint32_t adA, adB;
+        if (j < 3) {
+            adA = Rj + ubyte(m.x, j + 1);
+            adB = Cj + ubyte(m.y, j + 1);
+        } else {
+            adA = add_byte0(Rj, nm.x);
+            adB = add_byte0(Cj, nm.y);
+        }
+        const uint32_t nA = lds_ld16(adA);
+        const uint32_t nB = lds_ld16(adB);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t tA = xor_byte1(s.tA, z.x, j);
+        const uint32_t tB = xor_byte1(s.tB, z.y, j);
+        tie |= eq;
+        const uint32_t tj = acc ? tB : tA;
+        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+        s.acc = uj < tj;
+        eq = uj == tj;
+        s.R = Rj;
+        s.C = Cj;
+        s.tA = nA;
+        s.tB = nB;
+        __builtin_amdgcn_sched_barrier(0);
+        if (j == 0) {
+            done(fprev | (acc ? 0xFF000000u : 0u));
+        } else {
+            f |= acc ? (0xFFu << (8 * (j - 1))) : 0u;
+            asm volatile("" : "+v"(f));   // recorded here, not at the end of the dword
+        }
+        work(j);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    tie |= eq;
+    return f;
+}
+
+// dk bytes from row-step bytes 8 dk (each byte shifted right by 3 with its sign)
+__device__ __forceinline__ uint32_t pstream_dk(uint32_t e) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r |= ((uint32_t)(sbyte(e, j) >> 3) & 0xFFu) << (8 * j);
+    return r;
+}
+
+template <int L>
+__device__ __forceinline__ void run_potts_stream(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                                                 uint32_t sweep0, const LdsPlan &plan) {
+    constexpr int W = L / 4;                  // dwords per row
+    constexpr int NW = L * L / 4;             // dwords per lattice
+    constexpr int P = fast_lane_stride(L);    // lattice dwords between lanes
+    constexpr int B = kPStreamBatch;
+    constexpr int BPR = W / B;                // batches per row
+    constexpr int BPS = L * BPR;              // batches per sweep
+    constexpr uint32_t RS = pstream_lane_words(L) * 4u;   // ring bytes per lane
+    constexpr uint32_t RECB = 48u;                        // record bytes
+    static_assert(W % B == 0 && W >= 2 * B + 1, "streamed Potts walker shape");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthreads = blockDim.x;
+    const int np = nthreads / 64 - 1;         // producer waves
+    const int nch = it.nchains;
+    const bool active = (wave == 0) && (lane < nch);
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab + kPottsCompactGuard;
+    const uint32_t spin0 = lbase + (uint32_t)plan.off_spin;
+    const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
+    const uint32_t ctr = lbase + (uint32_t)plan.off_ctr;   // counters (see kCtrDone)
+
+    // the pair table from the 32-bit table in HBM (rows k, columns dk + 4)
+    {
+        const g_u32 *T = (const g_u32 *)p.table;
+        const int rows = 2 * p.N + 1;
+        if (tid == 0) *(lds_u16 *)(size_t)tab0 = 0;
+        for (int e = tid; e < 4 * rows; e += nthreads) {
+            const int k = e >> 2, j = (e & 3) + 1;
+            uint16_t v = 0;
+            if (k + j < rows) v = compact_entry(T[k * 9 + 4 + j], T[(k + j) * 9 + 4 - j]);
+            *(lds_u16 *)(size_t)(tab0 + 2u + 2u * (uint32_t)e) = v;
+        }
+    }
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const g_u8 *g = (const g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        const uint32_t v = (uint32_t)g[0] | ((uint32_t)g[p.C] << 8) | ((uint32_t)g[2 * (int64_t)p.C] << 16) |
+                           ((uint32_t)g[3 * (int64_t)p.C] << 24);
+        lds_st(spin0 + (uint32_t)(c * P + d) * 4u, v);
+    }
+    if (tid < kStreamCtrWords) lds_st(ctr + 4u * (uint32_t)tid, 0u);
+    __syncthreads();
+
+    const int n_sweeps = l.n_sweeps;
+    if (wave == 0) {
+        if (active) {
+            const uint32_t sb = spin0 + (uint32_t)(lane * P) * 4u;   // this lane's lattice
+            const uint32_t rb = ring0 + (uint32_t)lane * RS;          // this lane's records
+            auto row_addr = [&](int y) -> uint32_t { return sb + (uint32_t)(y * W) * 4u; };
+            FastState st{0, 0, 0, 0, false};
+            const int k0 = ((const g_i32 *)p.k)[it.chain0 + lane];
+            st.R = tab0 + 8u * (uint32_t)k0 - kPottsCompactBias;
+            st.C = st.R;
+            // After a wait gives up, the walker rewrites its records to reject
+            // every move (prefixes 2^32 - 1, which equal no entry; code 0, which
+            // stays in the guard before the table; no step, no state change).
+            auto neutralize = [&]() {
+                for (int w = 0; w < W; ++w) {
+                    lds_st4(rb + (uint32_t)w * RECB, make_uint4(~0u, ~0u, ~0u, ~0u));
+                    lds_st4(rb + (uint32_t)w * RECB + 16u, make_uint4(0u, 0u, 0u, 0u));
+                    lds_st4(rb + (uint32_t)w * RECB + 32u, make_uint4(0u, 0u, 0u, 0u));
+                }
+            };
+            bool ok = stream_wait(ctr, kCtrFormed, 1u, l.wait_polls);   // batch 0 of the launch
+            if (!ok) neutralize();
+            uint4 u_next = lds_ld4(rb);
+            uint4 nm = lds_ld4(rb + 16u);
+            uint4 nz = lds_ld4(rb + 32u);
+            st.tA = lds_ld16(st.R + ubyte(nm.x, 0));
+            st.tB = st.tA;
+            uint32_t c = 0;        // batches walked before the current one (wraps)
+            uint32_t formed = 0;   // batches formed, read a dword before the check
+            uint32_t fpend = 0;    // flips of sites 0..2 of the last dword walked, not yet in the lattice
+            uint32_t xpend = 0;    // that dword's state xor (old ^ proposal)
+            uint32_t apend = sb;   // that dword's address (nothing pending before the first dword)
+            for (int s = 0; s < n_sweeps && ok; ++s) {
+                const uint32_t sweep = sweep0 + (uint32_t)s;
+                for (int y = 0; y < L && ok; ++y) {
+                    const uint32_t vcur = row_addr(y);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const int q = w % B;
+                        // in a batch's last dword: batch c + 1 (whose first record this
+                        // dword's first site reads), none beyond the launch; the counter
+                        // was read a dword earlier
+                        if (q == B - 2) formed = lds_ld_sync(ctr + kCtrFormed);
+                        if (q == B - 1 && ok) {
+                            const uint32_t f1 = __builtin_amdgcn_readfirstlane(formed);
+                            const bool last = (y == L - 1 && s + 1 == n_sweeps && w + 1 == W);
+                            const uint32_t want = __builtin_amdgcn_readfirstlane(c) + (last ? 1u : 2u);
+                            if ((int32_t)(f1 - want) < 0) {
+                                ok = stream_wait(ctr, kCtrFormed, want, l.wait_polls);
+                                if (!ok) neutralize();
+                            }
+                            lds_order();
+                        }
+                        const uint4 m = nm, z = nz;
+                        const uint4 u = u_next;
+                        auto work = [&](int j) {
+                            if (j == 0) {
+                                const uint32_t slot = rb + (uint32_t)((w + 1) % W) * RECB;   // dword after this one
+                                u_next = lds_ld4(slot);
+                                nm = lds_ld4(slot + 16u);
+                                nz = lds_ld4(slot + 32u);
+                            }
+                        };
+                        // the previous dword's accepted sites take their proposals; after a
+                        // batch's last dword, and after a row's first dword (which the
+                        // row's last batch needs), the walker reports its progress
+                        auto done = [&](uint32_t fp) {
+                            lds_xor(apend, fp & xpend);
+                            if (q == 0 || w == 1) {
+                                lds_order();
+                                lds_st_sync(ctr + kCtrDone, c * (uint32_t)B + (uint32_t)q);
+                            }
+                        };
+                        const uint32_t R0 = st.R, C0 = st.C;
+                        const bool acc0 = st.acc;
+                        bool tie = false;
+                        uint32_t f = walk_dword_pstream(st, m, z, nm, u, fpend, tie, work, done);
+                        if (__builtin_amdgcn_ballot_w64(tie) != 0u) {
+                            // rare (about one dword in 4096 per chain): the whole wave redoes
+                            // the dword exactly (the redo agrees with the fast path wherever
+                            // the prefixes decide) and writes the whole record (0xff in byte j
+                            // for an accepted site j); site 3's outcome stays pending
+                            const RedoResult r = redo_compact_potts(
+                                R0, C0, acc0 ? 1u : 0u, m.x, m.y, pstream_dk(m.z), pstream_dk(m.w), z.x, z.y,
+                                __builtin_amdgcn_ubfe(nm.x, 0u, 8u), __builtin_amdgcn_ubfe(nm.y, 0u, 8u), u.x, u.y,
+                                u.z, u.w, tab0, p.table,
+                                (uint32_t)(y * W + w), sweep, (uint32_t)(it.chain0 + lane), p.seed_lo, p.seed_hi);
+                            st.R = r.s0;
+                            st.C = r.s1;
+                            st.tA = r.s2;
+                            st.tB = r.s3;
+                            st.acc = r.s4 != 0u;
+                            f = r.s5 & 0x00FFFFFFu;
+                        }
+                        fpend = f;
+                        xpend = z.z;
+                        apend = vcur + 4u * (uint32_t)w;
+                        if (q == B - 1) ++c;
+                    }
+                    if (y == L - 1 && l.record != kRecNone) {
+                        const uint32_t Rk = st.acc ? st.C : st.R;
+                        int bin = (int)((int32_t)(Rk + kPottsCompactBias - tab0) >> 3);
+                        bin = min(max(bin, 0), p.nbins - 1);   // in range even after an abort
+                        ((g_i32 *)p.hist)[(int64_t)bin * p.C + it.chain0 + lane] += 1;
+                    }
+                }
+            }
+            lds_xor(apend, (fpend | (st.acc ? 0xFF000000u : 0u)) & xpend);
+            const uint32_t Rk = st.acc ? st.C : st.R;
+            ((g_i32 *)p.k)[it.chain0 + lane] = (int)((int32_t)(Rk + kPottsCompactBias - tab0) >> 3);
+            ((g_i32 *)p.m)[it.chain0 + lane] = 0;
+        }
+    } else {
+        // producer wave i: batch bb of every sweep with bb = i mod np; lane r
+        // forms the records r, r + 64 of the batch (chain r / B, dword r mod B)
+        const int i = wave - 1;
+        bool ok = true;
+        for (int s = 0; s < n_sweeps && ok; ++s) {
+            const uint32_t sweep = sweep0 + (uint32_t)s;
+            for (int bb = i; bb < BPS; bb += np) {
+                const uint32_t c = (uint32_t)s * (uint32_t)BPS + (uint32_t)bb;   // batch since the launch began
+                const int y = bb / BPR, w0 = (bb - y * BPR) * B;
+                // everything that does not depend on the walker first (see the
+                // streamed Ising walker): draws, proposals and the terms of the
+                // old left, right and lower neighbours
+                uint4 uu[2], pe[2];
+                uint32_t cur[2], spv[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = lane + 64 * h;
+                    uu[h] = make_uint4(0, 0, 0, 0);
+                    pe[h] = make_uint4(0, 0, 0, 0);
+                    cur[h] = 0;
+                    spv[h] = 0;
+                    if (r < nch * B) {
+                        const int cc = r / B, x = w0 + (r - cc * B);
+                        const uint32_t chain = (uint32_t)(it.chain0 + cc);
+                        const uint32_t dw = (uint32_t)(y * W + x);
+                        const uint4 b0 = philox4x32_10(2u * dw, sweep, chain, 0u, p.seed_lo, p.seed_hi);
+                        const uint4 b1 = philox4x32_10(2u * dw + 1u, sweep, chain, 0u, p.seed_lo, p.seed_hi);
+                        const uint32_t t0 = (uint32_t)(((uint64_t)b0.x * 7u) >> 32);
+                        const uint32_t t1 = (uint32_t)(((uint64_t)b0.z * 7u) >> 32);
+                        const uint32_t t2 = (uint32_t)(((uint64_t)b1.x * 7u) >> 32);
+                        const uint32_t t3 = (uint32_t)(((uint64_t)b1.z * 7u) >> 32);
+                        uu[h] = make_uint4(min(b0.y, 0xFFFFFFFEu) >> 18, min(b0.w, 0xFFFFFFFEu) >> 18,
+                                           min(b1.y, 0xFFFFFFFEu) >> 18, min(b1.w, 0xFFFFFFFEu) >> 18);
+                        const uint32_t lb = spin0 + (uint32_t)(cc * P) * 4u;
+                        const uint32_t rowb = lb + (uint32_t)(y * W) * 4u;
+                        cur[h] = lds_ld(rowb + 4u * (uint32_t)x);
+                        const uint32_t prv = lds_ld(rowb + 4u * (uint32_t)(x == 0 ? W - 1 : x - 1));
+                        const uint32_t nxt = lds_ld(rowb + 4u * (uint32_t)(x + 1 == W ? x : x + 1));
+                        const uint32_t dn = lds_ld(lb + (uint32_t)((y + 1 == L ? 0 : y + 1) * W + x) * 4u);
+                        pe[h] = potts_pre(cur[h], prv, nxt, dn, t0 | (t1 << 8) | (t2 << 16) | (t3 << 24), x == 0,
+                                          x + 1 == W);
+                        if (x > 0) {
+                            // the previous dword's last proposal: its old state (byte 3 of
+                            // prv) moved by the draw of its second block
+                            const uint4 bp = philox4x32_10(2u * dw - 1u, sweep, chain, 0u, p.seed_lo, p.seed_hi);
+                            const uint32_t tp = (uint32_t)(((uint64_t)bp.z * 7u) >> 32);
+                            spv[h] = (((prv >> 24) + 1u + tp) & 7u) << 24;
+                        }
+                    }
+                }
+                // then the walker must have finished (y-1, w0+B-1) and, for a
+                // row's last batch, (y, 0)
+                const uint32_t g0 = c * (uint32_t)B;   // the batch's first dword since the launch began
+                const uint32_t want = (w0 + B == W) ? g0 - (uint32_t)w0 + 1u : g0 + (uint32_t)(B - W);
+                if (!stream_wait(ctr, kCtrDone, want, l.wait_polls)) {
+                    ok = false;
+                    break;
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = lane + 64 * h;
+                    if (r < nch * B) {
+                        const int cc = r / B, x = w0 + (r - cc * B);
+                        const uint32_t lb = spin0 + (uint32_t)(cc * P) * 4u;
+                        // the row above as this sweep left it
+                        const uint32_t up = lds_ld(lb + (uint32_t)((y == 0 ? L - 1 : y - 1) * W + x) * 4u);
+                        uint2 bd = potts_up(cur[h], up, pe[h]);
+                        if (x + 1 == W) bd = potts_row_end(bd, cur[h], pe[h].w, lds_ld(lb + (uint32_t)(y * W) * 4u));
+                        if (x == 0) bd.y += 1u;   // a row start: both candidates agree
+                        else bd.y = potts_left(bd.y, pe[h].z, spv[h]);
+                        CompactPottsBulk cb;
+                        potts_maps_c(bd, cb);
+                        potts_steps(bd, cb);
+                        const uint32_t e0 = (cb.k0 << 3) & 0xF8F8F8F8u, e1 = (cb.k1 << 3) & 0xF8F8F8F8u;
+                        const uint32_t slot = ring0 + (uint32_t)cc * RS + (uint32_t)x * RECB;
+                        lds_st4(slot, uu[h]);
+                        lds_st4(slot + 16u, make_uint4(cb.a0, cb.a1, e0, e1));
+                        lds_st4(slot + 32u, make_uint4(cb.z0, cb.z1, cur[h] ^ pe[h].w, 0u));
+                    }
+                }
+                // publish in order: after batch c - 1 (formed by the previous wave)
+                if (!stream_wait(ctr, kCtrFormed, c, l.wait_polls)) {
+                    ok = false;
+                    break;
+                }
+                if (lane == 0) lds_st_sync(ctr + kCtrFormed, c + 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && lds_ld_sync(ctr + kCtrAbort)) __hip_atomic_fetch_or(l.status, kStatusWaitExpired, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+    for (int j = tid; j < NW * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint32_t v = lds_ld(spin0 + (uint32_t)(c * P + d) * 4u);
+        g_u8 *g = (g_u8 *)p.spins + (int64_t)(4 * d) * p.C + it.chain0 + c;
+        g[0] = (uint8_t)v;
+        g[p.C] = (uint8_t)(v >> 8);
+        g[2 * (int64_t)p.C] = (uint8_t)(v >> 16);
+        g[3 * (int64_t)p.C] = (uint8_t)(v >> 24);
+    }
+}
+
 __device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                             const SweepLaunch &l, uint32_t sweep0,
                                                             const LdsPlan &plan) {
@@ -2140,7 +2515,10 @@ __device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, co
                   : run_potts_fast<24, false, false>(p, it, lds, l, sweep0, plan); return true;
     case 32: wide ? run_potts_fast<32, true, false>(p, it, lds, l, sweep0, plan)
                   : run_potts_fast<32, false, false>(p, it, lds, l, sweep0, plan); return true;
-    case 48: run_potts_fast<48, true, true>(p, it, lds, l, sweep0, plan); return true;
+    case 48:
+        if (stream_potts(p, it)) run_potts_stream<48>(p, it, lds, l, sweep0, plan);
+        else run_potts_fast<48, true, true>(p, it, lds, l, sweep0, plan);
+        return true;
     default: return false;
     }
 }
