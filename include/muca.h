@@ -156,7 +156,8 @@ typedef struct {
     int32_t walker;        /* walker of the problem's first work item: 0 generic, 1 byte-wise Ising or
                               multimagnetic, 2 packed Ising, 3 packed Ising on the compact table,
                               4 8-Potts, 5 8-Potts on the compact table, 6 streamed Ising,
-                              7 streamed 8-Potts on the compact table */
+                              7 streamed 8-Potts on the compact table, 8 streamed Ising on
+                              the compact table */
 } muca_launch_info;
 
 /* Bytes of device workspace that mucaInit needs for these problems.  (Not a

@@ -153,19 +153,38 @@ __host__ __device__ constexpr int pstream_lane_words(int L) { return (L / 4) * 1
 __host__ __device__ inline bool stream_potts(const ProbDev &p, const WorkItem &it) {
     return compact_potts(p) && it.nchains <= 32;
 }
+// The streamed compact Ising walker (run_ising_cstream): Ising L = 96 and 128
+// with up to 32 chains per workgroup; bit lattices, the compact table after a
+// 16-byte guard, per lane a ring of 48-byte records (one row at L = 96, 16
+// dwords at L = 128, where a row would not fit beside the table) and a
+// 16-byte pad.
+constexpr int kCStreamGuard = 16;
+__host__ __device__ constexpr int cstream_slots(int L) { return L / 4 > 24 ? 16 : L / 4; }
+__host__ __device__ constexpr int cstream_lane_words(int L) { return cstream_slots(L) * 12 + 4; }
+__host__ __device__ inline bool stream_compact_ising(const ProbDev &p, const WorkItem &it) {
+    return p.model == kIsing && (p.L == 96 || p.L == 128) && it.nchains <= 32;
+}
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
     l.off_tab = 0;
     const bool compact_i = compact_ising(p) && fast_ising_ok(p, n_producer_waves);
     const bool compact_p = compact_potts(p) && fast_potts_ok(p, n_producer_waves);
+    const bool cstream = compact_i && stream_compact_ising(p, it);
     const int tab = !p.table_lds ? 0
-                    : round_up(compact_i ? compact_table_bytes(p)
+                    : round_up(compact_i ? (cstream ? kCStreamGuard : 0) + compact_table_bytes(p)
                                          : compact_p ? kPottsGuardBytes + compact_potts_table_bytes(p)
                                                      : p.trows * p.tcols * 4,
                                16);
     l.off_spin = l.off_tab + tab;
     l.off_rows = 0;
     l.off_ctr = 0;
+    if (cstream) {
+        // bit lattices with an odd dword stride; record rings; counters
+        l.off_ring = l.off_spin + round_up(it.nchains * packed_bit_stride(p.L) * 4, 16);
+        l.off_ctr = l.off_ring + it.nchains * cstream_lane_words(p.L) * 4;
+        l.total = l.off_ctr + 4 * kStreamCtrWords;
+        return l;
+    }
     if (fast_ising_ok(p, n_producer_waves) && packed_ising(p, it)) {
         l.off_rows = l.off_spin + round_up(it.nchains * packed_bit_stride(p.L) * 4, 16);
         l.off_ring = l.off_rows + round_up(it.nchains * packed_row_stride(p.L) * 4, 16);
@@ -248,6 +267,7 @@ bool uses_fast_walker(const ProbDev &p, int n_producer_waves) {
 
 int walker_kind(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     if (fast_ising_ok(p, n_producer_waves)) {
+        if (p.model == kIsing && stream_compact_ising(p, it)) return 8;
         if (p.model == kIsing && packed_ising(p, it)) return compact_ising(p) ? 3 : 2;
         if (p.model == kIsing && stream_ising(p, it)) return 6;
         return 1;
@@ -1734,9 +1754,349 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
     }
 }
 
+// ------------------------------------------------------------------ streamed compact Ising walker
+//
+// The packed walker above unpacks rows, forms every dword's bulk and decodes
+// the compact table in one wave: about 139 cycles per site at L = 96 and 128.  Here,
+// as in the streamed Ising and Potts walkers, the helper waves form each
+// dword's complete record from the bit lattice once the walker has left the
+// row above (the draws' 14-bit prefixes, then column codes, row steps and
+// decode codes of both candidates), and the walker only decides sites and
+// xors each dword's flips, as a nibble, into the bit lattice.  Ties with the
+// 14-bit entries are redone exactly (redo_compact_dword).
+
+// The four sites of one dword: as walk_dword_pstream (compact decode, ties
+// folded a site later), with one flip bit per site: bit b0 + j for site j.
+// Returns the bits of sites 0..2; site 3's outcome is s.acc.
+template <class Work, class Done>
+__device__ __forceinline__ uint32_t walk_dword_cstream(FastState &s, const uint4 &m, const uint4 &z, const uint4 &nm,
+                                                       const uint4 &u, uint32_t b0, bool &tie, Work &&work,
+                                                       Done &&done) {
+    uint32_t f = 0;
+    bool eq = false;   // the previous site's tie, folded in a site later
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool acc = s.acc;
+        const uint32_t Rj = acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)(acc ? sbyte(m.w, j) : sbyte(m.z, j));
+        uint32_t adA, adB;
+        if (j < 3) {
+            adA = Rj + ubyte(m.x, j + 1);
+            adB = Cj + ubyte(m.y, j + 1);
+        } else {
+            adA = add_byte0(Rj, nm.x);
+            adB = add_byte0(Cj, nm.y);
+        }
+        const uint32_t nA = lds_ld16(adA);
+        const uint32_t nB = lds_ld16(adB);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t tA = xor_byte1(s.tA, z.x, j);
+        const uint32_t tB = xor_byte1(s.tB, z.y, j);
+        tie |= eq;
+        const uint32_t tj = acc ? tB : tA;
+        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+        s.acc = uj < tj;
+        eq = uj == tj;
+        s.R = Rj;
+        s.C = Cj;
+        s.tA = nA;
+        s.tB = nB;
+        __builtin_amdgcn_sched_barrier(0);
+        if (j == 0) {
+            done(acc);
+        } else {
+            f |= acc ? (1u << (b0 + (uint32_t)(j - 1))) : 0u;
+            asm volatile("" : "+v"(f));   // recorded here, not at the end of the dword
+        }
+        work(j);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    tie |= eq;
+    return f;
+}
+
+template <int L>
+__device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
+                                                  uint32_t sweep0, const LdsPlan &plan) {
+    constexpr int W = L / 4;                  // byte dwords (four sites) per row
+    constexpr int BPR = L / 32;               // bit dwords per row
+    constexpr int NB = L * BPR;               // bit dwords per lattice
+    constexpr int PB = packed_bit_stride(L);  // bit dwords between lanes
+    constexpr int B = kStreamBatch;
+    constexpr int BTR = W / B;                // batches per row
+    constexpr int BPS = L * BTR;              // batches per sweep
+    constexpr uint32_t RS = cstream_lane_words(L) * 4u;   // ring bytes per lane
+    constexpr uint32_t RECB = 48u;                        // record bytes
+    constexpr int R = cstream_slots(L);                   // record slots per lane: dword x uses slot x mod R
+    static_assert(W % B == 0 && W >= 2 * B + 1 && W % 8 == 0 && R >= 2 * B + 2, "streamed compact Ising walker shape");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nthreads = blockDim.x;
+    const int np = nthreads / 64 - 1;         // producer waves
+    const int nch = it.nchains;
+    const bool active = (wave == 0) && (lane < nch);
+    const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab + kCStreamGuard;
+    const uint32_t bits0 = lbase + (uint32_t)plan.off_spin;
+    const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
+    const uint32_t ctr = lbase + (uint32_t)plan.off_ctr;   // counters (see kCtrDone)
+    // compact rows (see run_ising_packed): R = tab0 + 4 kk - 4 for row kk = k / 2
+    auto kk_of = [&](uint32_t R) -> int { return (int)((int32_t)(R + 4u - tab0) >> 2); };
+
+    {
+        // the pair table, from the 32-bit table in HBM (rows kk, columns dk/2 + 2)
+        const g_u32 *T = (const g_u32 *)p.table;
+        const int rows = p.N + 1;
+        if (tid == 0) *(lds_u16 *)(size_t)tab0 = 0;
+        for (int e = tid; e < 2 * rows; e += nthreads) {
+            const int kk = e >> 1, j = (e & 1) + 1;
+            uint16_t v = 0;
+            if (kk + j < rows) v = compact_entry(T[kk * 5 + 2 + j], T[(kk + j) * 5 + 2 - j]);
+            *(lds_u16 *)(size_t)(tab0 + 2u + 2u * (uint32_t)e) = v;
+        }
+    }
+    // the lattice as bits: dword d of lane c holds sites 32d..32d+31
+    for (int j = tid; j < NB * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const g_u8 *g = (const g_u8 *)p.spins + (int64_t)(32 * d) * p.C + it.chain0 + c;
+        uint32_t v = 0;
+        for (int b = 0; b < 32; ++b) v |= (uint32_t)g[(int64_t)b * p.C] << b;
+        lds_st(bits0 + (uint32_t)(c * PB + d) * 4u, v);
+    }
+    if (tid < kStreamCtrWords) lds_st(ctr + 4u * (uint32_t)tid, 0u);
+    __syncthreads();
+
+    const int n_sweeps = l.n_sweeps;
+    if (wave == 0) {
+        if (active) {
+            const uint32_t bl = bits0 + (uint32_t)(lane * PB) * 4u;   // this lane's bits
+            const uint32_t rb = ring0 + (uint32_t)lane * RS;          // this lane's records
+            const uint32_t chain = (uint32_t)(it.chain0 + lane);
+            FastState st{0, 0, 0, 0, false};
+            const int k0 = ((const g_i32 *)p.k)[it.chain0 + lane];
+            st.R = tab0 + 4u * (uint32_t)(k0 >> 1) - 4u;
+            st.C = st.R;
+            // After a wait gives up, the walker rewrites its records to reject
+            // every move (prefixes 2^32 - 1, which no entry exceeds or equals;
+            // column code 4, the row's own entry; no step, no decode).
+            auto neutralize = [&]() {
+                for (int w = 0; w < R; ++w) {
+                    lds_st4(rb + (uint32_t)w * RECB, make_uint4(~0u, ~0u, ~0u, ~0u));
+                    lds_st4(rb + (uint32_t)w * RECB + 16u, make_uint4(0x04040404u, 0x04040404u, 0u, 0u));
+                    lds_st4(rb + (uint32_t)w * RECB + 32u, make_uint4(0u, 0u, 0u, 0u));
+                }
+            };
+            bool ok = stream_wait(ctr, kCtrFormed, 1u, l.wait_polls);   // batch 0 of the launch
+            if (!ok) neutralize();
+            uint4 u_next = lds_ld4(rb);
+            uint4 nm = lds_ld4(rb + 16u);
+            uint4 nz = lds_ld4(rb + 32u);
+            st.tA = lds_ld16(st.R + ubyte(nm.x, 0));
+            st.tB = st.tA;
+            uint32_t c = 0;        // batches walked before the current one (wraps)
+            uint32_t formed = 0;   // batches formed, read a dword before the check
+            uint32_t fpend = 0;    // flip bits of sites 0..2 of the last dword walked, not yet in the lattice
+            uint32_t apend = bl;   // that dword's bit word (nothing pending before the first dword)
+            for (int s = 0; s < n_sweeps && ok; ++s) {
+                const uint32_t sweep = sweep0 + (uint32_t)s;
+                for (int y = 0; y < L && ok; ++y) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const int q = w % B;
+                        // in a batch's last dword: batch c + 1 (whose first record this
+                        // dword's first site reads), none beyond the launch; the counter
+                        // was read a dword earlier
+                        if (q == B - 2) formed = lds_ld_sync(ctr + kCtrFormed);
+                        if (q == B - 1 && ok) {
+                            const uint32_t f1 = __builtin_amdgcn_readfirstlane(formed);
+                            const bool last = (y == L - 1 && s + 1 == n_sweeps && w + 1 == W);
+                            const uint32_t want = __builtin_amdgcn_readfirstlane(c) + (last ? 1u : 2u);
+                            if ((int32_t)(f1 - want) < 0) {
+                                ok = stream_wait(ctr, kCtrFormed, want, l.wait_polls);
+                                if (!ok) neutralize();
+                            }
+                            lds_order();
+                        }
+                        const uint4 m = nm, z = nz;
+                        const uint4 u = u_next;
+                        auto work = [&](int j) {
+                            if (j == 0) {
+                                const uint32_t slot = rb + (uint32_t)(((w + 1) % W) % R) * RECB;   // dword after this one
+                                u_next = lds_ld4(slot);
+                                nm = lds_ld4(slot + 16u);
+                                nz = lds_ld4(slot + 32u);
+                            }
+                        };
+                        // the previous dword's flips go into the bit lattice (its site 3 is
+                        // bit 4 ((w - 1) mod 8) + 3 of its word); after a batch's last dword,
+                        // and after a row's first dword (which the row's last batch needs),
+                        // the walker reports its progress
+                        const uint32_t b3prev = 4u * (uint32_t)((w + 7) % 8) + 3u;
+                        auto done = [&](bool acc3) {
+                            lds_xor(apend, fpend | (acc3 ? (1u << b3prev) : 0u));
+                            if (q == 0 || w == 1) {
+                                lds_order();
+                                lds_st_sync(ctr + kCtrDone, c * (uint32_t)B + (uint32_t)q);
+                            }
+                        };
+                        const uint32_t R0 = st.R, C0 = st.C;
+                        const bool acc0 = st.acc;
+                        bool tie = false;
+                        uint32_t f = walk_dword_cstream(st, m, z, nm, u, 4u * (uint32_t)(w % 8), tie, work, done);
+                        if (__builtin_amdgcn_ballot_w64(tie) != 0u) {
+                            // rare: the whole wave redoes the dword exactly (the redo agrees
+                            // with the fast path wherever the prefixes decide); its record
+                            // has bit j for an accepted site j; site 3's outcome stays pending
+                            const RedoResult r = redo_compact_dword(
+                                R0, C0, acc0 ? 1u : 0u, m.x, m.y, m.z, m.w, z.x, z.y, __builtin_amdgcn_ubfe(nm.x, 0u, 8u),
+                                __builtin_amdgcn_ubfe(nm.y, 0u, 8u), u.x, u.y, u.z, u.w, tab0, p.table,
+                                (uint32_t)(y * W + w), sweep, chain, p.seed_lo, p.seed_hi);
+                            st.R = r.s0;
+                            st.C = r.s1;
+                            st.tA = r.s2;
+                            st.tB = r.s3;
+                            st.acc = r.s4 != 0u;
+                            f = (r.s5 & 7u) << (4u * (uint32_t)(w % 8));
+                        }
+                        fpend = f;
+                        apend = bl + (uint32_t)(BPR * y + w / 8) * 4u;
+                        if (q == B - 1) ++c;
+                    }
+                    if (y == L - 1 && l.record != kRecNone) {
+                        const uint32_t Rk = st.acc ? st.C : st.R;
+                        const int bin = min(max(2 * kk_of(Rk), 0), p.nbins - 1);   // in range even after an abort
+                        const int64_t cidx = (int64_t)bin * p.C + it.chain0 + lane;
+                        ((g_i32 *)p.hist)[cidx] += 1;
+                        if (l.record == kRecProd) {
+                            int ones = 0;
+                            for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
+                            // the last dword's flips are still pending
+                            const uint32_t old = lds_ld(apend);
+                            const uint32_t fl = fpend | (st.acc ? (1u << (4u * (uint32_t)((W - 1) % 8) + 3u)) : 0u);
+                            ones += __builtin_popcount(old ^ fl) - __builtin_popcount(old);
+                            const int mm = 2 * ones - L * L;
+                            ((g_i64 *)p.sabs)[cidx] += (int64_t)(mm < 0 ? -mm : mm);
+                        }
+                    }
+                }
+            }
+            lds_xor(apend, fpend | (st.acc ? (1u << (4u * (uint32_t)((W - 1) % 8) + 3u)) : 0u));
+            const uint32_t Rk = st.acc ? st.C : st.R;
+            ((g_i32 *)p.k)[it.chain0 + lane] = 2 * kk_of(Rk);
+            int ones = 0;
+            for (int dd = 0; dd < NB; ++dd) ones += __builtin_popcount(lds_ld(bl + 4u * dd));
+            ((g_i32 *)p.m)[it.chain0 + lane] = 2 * ones - L * L;
+        }
+    } else {
+        // producer wave i: batch bb of every sweep with bb = i mod np; lane r
+        // forms the records r, r + 64 of the batch (chain r / B, dword r mod B)
+        const int i = wave - 1;
+        bool ok = true;
+        for (int s = 0; s < n_sweeps && ok; ++s) {
+            const uint32_t sweep = sweep0 + (uint32_t)s;
+            for (int bb = i; bb < BPS; bb += np) {
+                const uint32_t c = (uint32_t)s * (uint32_t)BPS + (uint32_t)bb;   // batch since the launch began
+                const int y = bb / BTR, w0 = (bb - y * BTR) * B;
+                // first what does not depend on the walker: the draws, and the
+                // counts over the old left, right and lower neighbours (see the
+                // streamed Ising walker)
+                uint4 uu[2];
+                uint2 pre[2];
+                uint32_t cur[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = lane + 64 * h;
+                    uu[h] = make_uint4(0, 0, 0, 0);
+                    pre[h] = make_uint2(0, 0);
+                    cur[h] = 0;
+                    if (r < nch * B) {
+                        const int cc = r / B, x = w0 + (r - cc * B);
+                        const uint4 v = philox4x32_10((uint32_t)(y * W + x), sweep, (uint32_t)(it.chain0 + cc), 0u,
+                                                      p.seed_lo, p.seed_hi);
+                        uu[h] = make_uint4(min(v.x, 0xFFFFFFFEu) >> 18, min(v.y, 0xFFFFFFFEu) >> 18,
+                                           min(v.z, 0xFFFFFFFEu) >> 18, min(v.w, 0xFFFFFFFEu) >> 18);
+                        const uint32_t lb = bits0 + (uint32_t)(cc * PB) * 4u;
+                        const uint32_t rowb = lb + (uint32_t)(y * BPR) * 4u;
+                        const uint32_t word = lds_ld(rowb + 4u * (uint32_t)(x / 8));
+                        const uint32_t sh = 4u * (uint32_t)(x % 8);
+                        cur[h] = spread_nibble((word >> sh) & 15u);
+                        // left neighbour of site 0 (bit 31 of the previous word, or the
+                        // row's last site at a row start) and right neighbour of site 3
+                        const uint32_t lw = (x % 8 == 0) ? lds_ld(rowb + 4u * (uint32_t)((x == 0 ? W : x) / 8 - 1)) : word;
+                        const uint32_t lbit = (lw >> ((sh + 31u) & 31u)) & 1u;
+                        const uint32_t rw = (x % 8 == 7 && x + 1 < W) ? lds_ld(rowb + 4u * (uint32_t)(x / 8 + 1)) : word;
+                        const uint32_t rbit = (rw >> ((sh + 4u) & 31u)) & 1u;
+                        const uint32_t dw = lds_ld(lb + (uint32_t)(((y + 1 == L) ? 0 : y + 1) * BPR + x / 8) * 4u);
+                        const uint32_t dn = spread_nibble((dw >> sh) & 15u);
+                        pre[h] = ising_pre(cur[h], lbit << 24, rbit, dn, x == 0, x + 1 == W);
+                    }
+                }
+                // then the walker must have finished (y-1, w0+B-1) and, for a
+                // row's last batch, (y, 0); with fewer slots than dwords per row
+                // it must also have finished the dwords whose records these
+                // replace (x - R for dword x), which implies both
+                const uint32_t g0 = c * (uint32_t)B;   // the batch's first dword since the launch began
+                const uint32_t want = (R < W) ? g0 + (uint32_t)(B - R)
+                                    : (w0 + B == W) ? g0 - (uint32_t)w0 + 1u : g0 + (uint32_t)(B - W);
+                if (!stream_wait(ctr, kCtrDone, want, l.wait_polls)) {
+                    ok = false;
+                    break;
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = lane + 64 * h;
+                    if (r < nch * B) {
+                        const int cc = r / B, x = w0 + (r - cc * B);
+                        const uint32_t lb = bits0 + (uint32_t)(cc * PB) * 4u;
+                        const uint32_t sh = 4u * (uint32_t)(x % 8);
+                        // the row above as this sweep left it
+                        const uint32_t uw = lds_ld(lb + (uint32_t)((y == 0 ? L - 1 : y - 1) * BPR + x / 8) * 4u);
+                        const uint32_t xu = cur[h] ^ spread_nibble((uw >> sh) & 15u);
+                        uint32_t d0 = pre[h].x + xu, d1 = pre[h].y + xu;
+                        if (x + 1 == W) {
+                            // right neighbour of the row's last site: the row's first site, this sweep
+                            const uint32_t first = lds_ld(lb + (uint32_t)(y * BPR) * 4u) & 1u;
+                            const uint32_t cr = (cur[h] ^ (first << 24)) & 0xFF000000u;
+                            d0 += cr;
+                            d1 += cr;
+                        }
+                        CompactBulk fb;
+                        compact_cols(BulkDiff{cur[h], d0, d1}, fb);
+                        compact_steps(BulkDiff{cur[h], d0, d1}, fb);
+                        const uint32_t slot = ring0 + (uint32_t)cc * RS + (uint32_t)(x % R) * RECB;
+                        lds_st4(slot, uu[h]);
+                        lds_st4(slot + 16u, make_uint4(fb.a0, fb.a1, fb.e0, fb.e1));
+                        lds_st4(slot + 32u, make_uint4(fb.z0, fb.z1, 0u, 0u));
+                    }
+                }
+                // publish in order: after batch c - 1 (formed by the previous wave)
+                if (!stream_wait(ctr, kCtrFormed, c, l.wait_polls)) {
+                    ok = false;
+                    break;
+                }
+                if (lane == 0) lds_st_sync(ctr + kCtrFormed, c + 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && lds_ld_sync(ctr + kCtrAbort)) __hip_atomic_fetch_or(l.status, kStatusWaitExpired, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+    // bits back to bytes in HBM
+    for (int j = tid; j < NB * nch; j += nthreads) {
+        const int d = j / nch, c = j - d * nch;
+        const uint32_t v = lds_ld(bits0 + (uint32_t)(c * PB + d) * 4u);
+        g_u8 *g = (g_u8 *)p.spins + (int64_t)(32 * d) * p.C + it.chain0 + c;
+        for (int b = 0; b < 32; ++b) g[(int64_t)b * p.C] = (uint8_t)((v >> b) & 1u);
+    }
+}
+
 template <bool MAG>
 __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                       const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
+    if (!MAG && stream_compact_ising(p, it)) {
+        if (p.L == 96) run_ising_cstream<96>(p, it, lds, l, sweep0, plan);
+        else run_ising_cstream<128>(p, it, lds, l, sweep0, plan);
+        return true;
+    }
     if (!MAG && packed_ising(p, it)) {
         switch (p.L) {
         case 64: run_ising_packed<64, false>(p, it, lds, l, sweep0, plan); return true;
