@@ -2089,13 +2089,15 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
     }
 }
 
-template <bool MAG>
+template <bool MAG, bool CS>
 __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const WorkItem &it, char *lds,
                                                       const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
-    if (!MAG && stream_compact_ising(p, it)) {
-        if (p.L == 96) run_ising_cstream<96>(p, it, lds, l, sweep0, plan);
-        else run_ising_cstream<128>(p, it, lds, l, sweep0, plan);
-        return true;
+    if constexpr (CS) {
+        if (!MAG && stream_compact_ising(p, it)) {
+            if (p.L == 96) run_ising_cstream<96>(p, it, lds, l, sweep0, plan);
+            else run_ising_cstream<128>(p, it, lds, l, sweep0, plan);
+            return true;
+        }
     }
     if (!MAG && packed_ising(p, it)) {
         switch (p.L) {
@@ -2885,7 +2887,7 @@ __device__ __forceinline__ bool run_potts_fast_if_supported(const ProbDev &p, co
 
 // ------------------------------------------------------------------ work item driver
 
-template <int MODEL, bool SPIN_LDS, bool TAB_LDS>
+template <int MODEL, bool SPIN_LDS, bool TAB_LDS, bool CS>
 __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                          uint32_t sweep0) {
     const LdsPlan plan = lds_plan(p, it, l.n_producer_waves);
@@ -2909,7 +2911,7 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
         tab.base = (const g_u32 *)p.table;
     }
     if ((MODEL == kIsing || MODEL == kIsingMag) && SPIN_LDS && TAB_LDS && fast_ising_ok(p, l.n_producer_waves)) {
-        if (run_fast_if_supported<MODEL == kIsingMag>(p, it, lds, l, sweep0, plan)) return;
+        if (run_fast_if_supported<MODEL == kIsingMag, CS>(p, it, lds, l, sweep0, plan)) return;
     }
     if (MODEL == kPotts && SPIN_LDS && TAB_LDS && fast_potts_ok(p, l.n_producer_waves)) {
         if (run_potts_fast_if_supported(p, it, lds, l, sweep0, plan)) return;
@@ -2985,6 +2987,11 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     }
 }
 
+// One instantiation with the streamed compact Ising walker (CS) and one
+// without: the walker adds code that, compiled into the same kernel, slows
+// the other walkers by about 2 %, so launches without such items use the
+// kernel without it.
+template <bool CS>
 __global__ void __launch_bounds__(64 * (1 + kMaxProducerWaves)) sweep_kernel(SweepLaunch l) {
     extern __shared__ __align__(16) char lds[];
     const WorkItem it = l.items[blockIdx.x];
@@ -2992,27 +2999,27 @@ __global__ void __launch_bounds__(64 * (1 + kMaxProducerWaves)) sweep_kernel(Swe
     const uint32_t sweep0 = *l.sweep_ctr;
     if (p.model == kIsing) {
         if (p.spin_lds) {
-            if (p.table_lds) run_item<kIsing, true, true>(p, it, lds, l, sweep0);
-            else run_item<kIsing, true, false>(p, it, lds, l, sweep0);
+            if (p.table_lds) run_item<kIsing, true, true, CS>(p, it, lds, l, sweep0);
+            else run_item<kIsing, true, false, CS>(p, it, lds, l, sweep0);
         } else {
-            if (p.table_lds) run_item<kIsing, false, true>(p, it, lds, l, sweep0);
-            else run_item<kIsing, false, false>(p, it, lds, l, sweep0);
+            if (p.table_lds) run_item<kIsing, false, true, CS>(p, it, lds, l, sweep0);
+            else run_item<kIsing, false, false, CS>(p, it, lds, l, sweep0);
         }
     } else if (p.model == kIsingMag) {
         if (p.spin_lds) {
-            if (p.table_lds) run_item<kIsingMag, true, true>(p, it, lds, l, sweep0);
-            else run_item<kIsingMag, true, false>(p, it, lds, l, sweep0);
+            if (p.table_lds) run_item<kIsingMag, true, true, CS>(p, it, lds, l, sweep0);
+            else run_item<kIsingMag, true, false, CS>(p, it, lds, l, sweep0);
         } else {
-            if (p.table_lds) run_item<kIsingMag, false, true>(p, it, lds, l, sweep0);
-            else run_item<kIsingMag, false, false>(p, it, lds, l, sweep0);
+            if (p.table_lds) run_item<kIsingMag, false, true, CS>(p, it, lds, l, sweep0);
+            else run_item<kIsingMag, false, false, CS>(p, it, lds, l, sweep0);
         }
     } else {
         if (p.spin_lds) {
-            if (p.table_lds) run_item<kPotts, true, true>(p, it, lds, l, sweep0);
-            else run_item<kPotts, true, false>(p, it, lds, l, sweep0);
+            if (p.table_lds) run_item<kPotts, true, true, CS>(p, it, lds, l, sweep0);
+            else run_item<kPotts, true, false, CS>(p, it, lds, l, sweep0);
         } else {
-            if (p.table_lds) run_item<kPotts, false, true>(p, it, lds, l, sweep0);
-            else run_item<kPotts, false, false>(p, it, lds, l, sweep0);
+            if (p.table_lds) run_item<kPotts, false, true, CS>(p, it, lds, l, sweep0);
+            else run_item<kPotts, false, false, CS>(p, it, lds, l, sweep0);
         }
     }
 }
@@ -3183,13 +3190,19 @@ hipError_t launch_energy(const ProbDev &p, hipStream_t s) {
 }
 
 hipError_t configure_sweep_kernel(int max_lds_bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
 }
 
-hipError_t launch_sweep(const SweepLaunch &l, hipStream_t s) {
+hipError_t launch_sweep(const SweepLaunch &l, bool streamed_compact_ising, hipStream_t s) {
     const int threads = 64 * (1 + l.n_producer_waves);
-    hipLaunchKernelGGL(sweep_kernel, dim3(l.n_items), dim3(threads), l.lds_bytes, s, l);
+    if (streamed_compact_ising)
+        hipLaunchKernelGGL(sweep_kernel<true>, dim3(l.n_items), dim3(threads), l.lds_bytes, s, l);
+    else
+        hipLaunchKernelGGL(sweep_kernel<false>, dim3(l.n_items), dim3(threads), l.lds_bytes, s, l);
     return hipGetLastError();
 }
 
