@@ -1,7 +1,9 @@
-"""Parity of the packed Ising walker with the compact acceptance table
-(Ising L = 96 and 128, whose 32-bit tables do not fit in LDS beside the
-lattices) against the oracle, through the C ABI.  The compact walker decides
-most moves from a 14-bit prefix of the threshold and redoes a dword exactly
+"""Parity of the walkers on the compact acceptance table (Ising L = 96 and
+128, whose 32-bit tables do not fit in LDS beside the lattices, and 8-Potts
+L = 48) against the oracle, through the C ABI.  Up to 32 chains per workgroup
+the streamed walkers run these problems, above that the packed Ising and
+byte-wise Potts walkers; the cases cover both.  The compact walkers decide
+most moves from a 14-bit prefix of the threshold and redo a dword exactly
 (full threshold from HBM, draw regenerated) when a draw's prefix equals it,
 about once per 2^14 sites: at these sizes and lengths every test passes that
 path hundreds of times, and every trajectory must still equal the oracle's bit
