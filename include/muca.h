@@ -157,7 +157,8 @@ typedef struct {
                               multimagnetic, 2 packed Ising, 3 packed Ising on the compact table,
                               4 8-Potts, 5 8-Potts on the compact table, 6 streamed Ising,
                               7 streamed 8-Potts on the compact table, 8 streamed Ising on
-                              the compact table */
+                              the compact table, 9 streamed Ising on bit lattices (L = 64,
+                              more than 16 chains per workgroup) */
 } muca_launch_info;
 
 /* Bytes of device workspace that mucaInit needs for these problems.  (Not a

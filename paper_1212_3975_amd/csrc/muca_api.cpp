@@ -494,7 +494,7 @@ muca_status enqueue_sweep(muca_ctx ctx, int64_t n_sweeps, int record, bool timed
     }
     bool cstream = false;
     for (const WorkItem &it : ctx->items)
-        cstream = cstream || walker_kind(ctx->h_probdev[it.prob], it, ctx->n_producer_waves) == 8;
+        cstream = cstream || walker_kind(ctx->h_probdev[it.prob], it, ctx->n_producer_waves) >= 8;
     HIPCHECK(ctx, launch_sweep(l, cstream, ctx->stream));
     if (timed) {
         HIPCHECK(ctx, hipEventRecord(e1, ctx->stream));

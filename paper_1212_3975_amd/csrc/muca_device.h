@@ -84,8 +84,9 @@ hipError_t configure_sweep_kernel(int max_lds_bytes);
 // Launchers (muca_kernels.hip).  All enqueue on `stream` and return the HIP status.
 hipError_t launch_init(const ProbDev &p, int chain_begin, int n_chains, hipStream_t stream);
 hipError_t launch_energy(const ProbDev &p, hipStream_t stream);
-// streamed_compact_ising: some work item runs the streamed compact Ising walker
-// (walker_kind 8); the launch then takes the kernel that contains it.
+// streamed_compact_ising: some work item runs the streamed Ising walker on bit
+// lattices (walker_kind 8 or 9); the launch then takes the kernel that
+// contains it.
 hipError_t launch_sweep(const SweepLaunch &l, bool streamed_compact_ising, hipStream_t stream);
 hipError_t launch_advance(uint32_t *sweep_ctr, uint32_t n, hipStream_t stream);
 hipError_t launch_merge(const ProbDev *probs, const MergeItem *items, int n_items, int production,

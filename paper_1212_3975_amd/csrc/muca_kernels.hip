@@ -158,11 +158,18 @@ __host__ __device__ inline bool stream_potts(const ProbDev &p, const WorkItem &i
 // 16-byte guard, per lane a ring of 48-byte records (one row at L = 96, 16
 // dwords at L = 128, where a row would not fit beside the table) and a
 // 16-byte pad.
+// The same walker on the 32-bit table runs Ising L = 64 with 17 to 64 chains
+// per workgroup (32-byte records, one row of them per lane).
 constexpr int kCStreamGuard = 16;
 __host__ __device__ constexpr int cstream_slots(int L) { return L / 4 > 24 ? 16 : L / 4; }
-__host__ __device__ constexpr int cstream_lane_words(int L) { return cstream_slots(L) * 12 + 4; }
+__host__ __device__ constexpr int cstream_lane_words(int L, bool compact) {
+    return cstream_slots(L) * (compact ? 12 : 8) + 4;
+}
 __host__ __device__ inline bool stream_compact_ising(const ProbDev &p, const WorkItem &it) {
     return p.model == kIsing && (p.L == 96 || p.L == 128) && it.nchains <= 32;
+}
+__host__ __device__ inline bool stream_bit_ising(const ProbDev &p, const WorkItem &it) {
+    return p.model == kIsing && p.L == 64 && it.nchains > 16;
 }
 __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     LdsPlan l;
@@ -178,10 +185,10 @@ __host__ __device__ inline LdsPlan lds_plan(const ProbDev &p, const WorkItem &it
     l.off_spin = l.off_tab + tab;
     l.off_rows = 0;
     l.off_ctr = 0;
-    if (cstream) {
+    if (cstream || (fast_ising_ok(p, n_producer_waves) && stream_bit_ising(p, it))) {
         // bit lattices with an odd dword stride; record rings; counters
         l.off_ring = l.off_spin + round_up(it.nchains * packed_bit_stride(p.L) * 4, 16);
-        l.off_ctr = l.off_ring + it.nchains * cstream_lane_words(p.L) * 4;
+        l.off_ctr = l.off_ring + it.nchains * cstream_lane_words(p.L, cstream) * 4;
         l.total = l.off_ctr + 4 * kStreamCtrWords;
         return l;
     }
@@ -268,6 +275,7 @@ bool uses_fast_walker(const ProbDev &p, int n_producer_waves) {
 int walker_kind(const ProbDev &p, const WorkItem &it, int n_producer_waves) {
     if (fast_ising_ok(p, n_producer_waves)) {
         if (p.model == kIsing && stream_compact_ising(p, it)) return 8;
+        if (p.model == kIsing && stream_bit_ising(p, it)) return 9;
         if (p.model == kIsing && packed_ising(p, it)) return compact_ising(p) ? 3 : 2;
         if (p.model == kIsing && stream_ising(p, it)) return 6;
         return 1;
@@ -1815,7 +1823,49 @@ __device__ __forceinline__ uint32_t walk_dword_cstream(FastState &s, const uint4
     return f;
 }
 
-template <int L>
+// The four sites of one dword on the 32-bit table (Ising L = 64): as
+// walk_dword_stream, with one flip bit per site (bit b0 + j for site j).
+template <class Work, class Done>
+__device__ __forceinline__ uint32_t walk_dword_bstream(FastState &s, const uint4 &m, const uint4 &nm, const uint4 &u,
+                                                       uint32_t b0, Work &&work, Done &&done) {
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool acc = s.acc;
+        const uint32_t Rj = acc ? s.C : s.R;
+        const uint32_t Cj = Rj + (uint32_t)(acc ? sbyte(m.w, j) : sbyte(m.z, j));
+        uint32_t adA, adB;
+        if (j < 3) {
+            adA = Rj + ubyte(m.x, j + 1);
+            adB = Cj + ubyte(m.y, j + 1);
+        } else {
+            adA = add_byte0(Rj, nm.x);
+            adB = add_byte0(Cj, nm.y);
+        }
+        const uint32_t nA = lds_ld(adA);
+        const uint32_t nB = lds_ld(adB);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t tj = acc ? s.tB : s.tA;
+        const uint32_t uj = (j == 0) ? u.x : (j == 1) ? u.y : (j == 2) ? u.z : u.w;
+        s.acc = uj < tj;
+        s.R = Rj;
+        s.C = Cj;
+        s.tA = nA;
+        s.tB = nB;
+        __builtin_amdgcn_sched_barrier(0);
+        if (j == 0) {
+            done(acc);
+        } else {
+            f |= acc ? (1u << (b0 + (uint32_t)(j - 1))) : 0u;
+            asm volatile("" : "+v"(f));   // recorded here, not at the end of the dword
+        }
+        work(j);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return f;
+}
+
+template <int L, bool COMPACT>
 __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkItem &it, char *lds, const SweepLaunch &l,
                                                   uint32_t sweep0, const LdsPlan &plan) {
     constexpr int W = L / 4;                  // byte dwords (four sites) per row
@@ -1825,9 +1875,10 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
     constexpr int B = kStreamBatch;
     constexpr int BTR = W / B;                // batches per row
     constexpr int BPS = L * BTR;              // batches per sweep
-    constexpr uint32_t RS = cstream_lane_words(L) * 4u;   // ring bytes per lane
-    constexpr uint32_t RECB = 48u;                        // record bytes
+    constexpr uint32_t RS = cstream_lane_words(L, COMPACT) * 4u;   // ring bytes per lane
+    constexpr uint32_t RECB = COMPACT ? 48u : 32u;                 // record bytes
     constexpr int R = cstream_slots(L);                   // record slots per lane: dword x uses slot x mod R
+    constexpr int HR = COMPACT ? 2 : 4;                   // records per helper lane and batch (32 or 64 chains)
     static_assert(W % B == 0 && W >= 2 * B + 1 && W % 8 == 0 && R >= 2 * B + 2, "streamed compact Ising walker shape");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nthreads = blockDim.x;
@@ -1835,14 +1886,19 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
     const int nch = it.nchains;
     const bool active = (wave == 0) && (lane < nch);
     const uint32_t lbase = (uint32_t)(size_t)(__attribute__((address_space(3))) char *)lds;
-    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab + kCStreamGuard;
+    const uint32_t tab0 = lbase + (uint32_t)plan.off_tab + (COMPACT ? kCStreamGuard : 0u);
     const uint32_t bits0 = lbase + (uint32_t)plan.off_spin;
     const uint32_t ring0 = lbase + (uint32_t)plan.off_ring;
     const uint32_t ctr = lbase + (uint32_t)plan.off_ctr;   // counters (see kCtrDone)
-    // compact rows (see run_ising_packed): R = tab0 + 4 kk - 4 for row kk = k / 2
-    auto kk_of = [&](uint32_t R) -> int { return (int)((int32_t)(R + 4u - tab0) >> 2); };
+    // rows kk = k / 2: compact R = tab0 + 4 kk - 4 (see run_ising_packed), else
+    // 20 kk (five words); the 32-bit table is already in LDS
+    auto row_of = [&](int kk) -> uint32_t { return COMPACT ? tab0 + 4u * (uint32_t)kk - 4u : tab0 + 20u * (uint32_t)kk; };
+    auto kk_of = [&](uint32_t R) -> int {
+        return COMPACT ? (int)((int32_t)(R + 4u - tab0) >> 2) : (int)((int32_t)(R - tab0) / 20);
+    };
+    auto read_t = [&](uint32_t a) -> uint32_t { return COMPACT ? lds_ld16(a) : lds_ld(a); };
 
-    {
+    if constexpr (COMPACT) {
         // the pair table, from the 32-bit table in HBM (rows kk, columns dk/2 + 2)
         const g_u32 *T = (const g_u32 *)p.table;
         const int rows = p.N + 1;
@@ -1873,24 +1929,26 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
             const uint32_t chain = (uint32_t)(it.chain0 + lane);
             FastState st{0, 0, 0, 0, false};
             const int k0 = ((const g_i32 *)p.k)[it.chain0 + lane];
-            st.R = tab0 + 4u * (uint32_t)(k0 >> 1) - 4u;
+            st.R = row_of(k0 >> 1);
             st.C = st.R;
             // After a wait gives up, the walker rewrites its records to reject
-            // every move (prefixes 2^32 - 1, which no entry exceeds or equals;
-            // column code 4, the row's own entry; no step, no decode).
+            // every move (draws 2^32 - 1, which no threshold exceeds and no
+            // 14-bit entry equals; compact code 4, the row's own entry, or
+            // column 0; no step, no decode).
             auto neutralize = [&]() {
+                const uint32_t a = COMPACT ? 0x04040404u : 0u;
                 for (int w = 0; w < R; ++w) {
                     lds_st4(rb + (uint32_t)w * RECB, make_uint4(~0u, ~0u, ~0u, ~0u));
-                    lds_st4(rb + (uint32_t)w * RECB + 16u, make_uint4(0x04040404u, 0x04040404u, 0u, 0u));
-                    lds_st4(rb + (uint32_t)w * RECB + 32u, make_uint4(0u, 0u, 0u, 0u));
+                    lds_st4(rb + (uint32_t)w * RECB + 16u, make_uint4(a, a, 0u, 0u));
+                    if (COMPACT) lds_st4(rb + (uint32_t)w * RECB + 32u, make_uint4(0u, 0u, 0u, 0u));
                 }
             };
             bool ok = stream_wait(ctr, kCtrFormed, 1u, l.wait_polls);   // batch 0 of the launch
             if (!ok) neutralize();
             uint4 u_next = lds_ld4(rb);
             uint4 nm = lds_ld4(rb + 16u);
-            uint4 nz = lds_ld4(rb + 32u);
-            st.tA = lds_ld16(st.R + ubyte(nm.x, 0));
+            uint4 nz = COMPACT ? lds_ld4(rb + 32u) : make_uint4(0, 0, 0, 0);
+            st.tA = read_t(st.R + ubyte(nm.x, 0));
             st.tB = st.tA;
             uint32_t c = 0;        // batches walked before the current one (wraps)
             uint32_t formed = 0;   // batches formed, read a dword before the check
@@ -1923,7 +1981,7 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                                 const uint32_t slot = rb + (uint32_t)(((w + 1) % W) % R) * RECB;   // dword after this one
                                 u_next = lds_ld4(slot);
                                 nm = lds_ld4(slot + 16u);
-                                nz = lds_ld4(slot + 32u);
+                                if (COMPACT) nz = lds_ld4(slot + 32u);
                             }
                         };
                         // the previous dword's flips go into the bit lattice (its site 3 is
@@ -1938,10 +1996,14 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                                 lds_st_sync(ctr + kCtrDone, c * (uint32_t)B + (uint32_t)q);
                             }
                         };
+                        uint32_t f;
+                        if constexpr (!COMPACT) {
+                            f = walk_dword_bstream(st, m, nm, u, 4u * (uint32_t)(w % 8), work, done);
+                        } else {
                         const uint32_t R0 = st.R, C0 = st.C;
                         const bool acc0 = st.acc;
                         bool tie = false;
-                        uint32_t f = walk_dword_cstream(st, m, z, nm, u, 4u * (uint32_t)(w % 8), tie, work, done);
+                        f = walk_dword_cstream(st, m, z, nm, u, 4u * (uint32_t)(w % 8), tie, work, done);
                         if (__builtin_amdgcn_ballot_w64(tie) != 0u) {
                             // rare: the whole wave redoes the dword exactly (the redo agrees
                             // with the fast path wherever the prefixes decide); its record
@@ -1956,6 +2018,7 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                             st.tB = r.s3;
                             st.acc = r.s4 != 0u;
                             f = (r.s5 & 7u) << (4u * (uint32_t)(w % 8));
+                        }
                         }
                         fpend = f;
                         apend = bl + (uint32_t)(BPR * y + w / 8) * 4u;
@@ -1988,7 +2051,7 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
         }
     } else {
         // producer wave i: batch bb of every sweep with bb = i mod np; lane r
-        // forms the records r, r + 64 of the batch (chain r / B, dword r mod B)
+        // forms the records r, r + 64, ... of the batch (chain r / B, dword r mod B)
         const int i = wave - 1;
         bool ok = true;
         for (int s = 0; s < n_sweeps && ok; ++s) {
@@ -1999,11 +2062,11 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                 // first what does not depend on the walker: the draws, and the
                 // counts over the old left, right and lower neighbours (see the
                 // streamed Ising walker)
-                uint4 uu[2];
-                uint2 pre[2];
-                uint32_t cur[2];
+                uint4 uu[HR];
+                uint2 pre[HR];
+                uint32_t cur[HR];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < HR; ++h) {
                     const int r = lane + 64 * h;
                     uu[h] = make_uint4(0, 0, 0, 0);
                     pre[h] = make_uint2(0, 0);
@@ -2012,8 +2075,10 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                         const int cc = r / B, x = w0 + (r - cc * B);
                         const uint4 v = philox4x32_10((uint32_t)(y * W + x), sweep, (uint32_t)(it.chain0 + cc), 0u,
                                                       p.seed_lo, p.seed_hi);
-                        uu[h] = make_uint4(min(v.x, 0xFFFFFFFEu) >> 18, min(v.y, 0xFFFFFFFEu) >> 18,
-                                           min(v.z, 0xFFFFFFFEu) >> 18, min(v.w, 0xFFFFFFFEu) >> 18);
+                        uu[h] = make_uint4(min(v.x, 0xFFFFFFFEu), min(v.y, 0xFFFFFFFEu), min(v.z, 0xFFFFFFFEu),
+                                           min(v.w, 0xFFFFFFFEu));
+                        // the compact walker compares the top 14 bits
+                        if (COMPACT) uu[h] = make_uint4(uu[h].x >> 18, uu[h].y >> 18, uu[h].z >> 18, uu[h].w >> 18);
                         const uint32_t lb = bits0 + (uint32_t)(cc * PB) * 4u;
                         const uint32_t rowb = lb + (uint32_t)(y * BPR) * 4u;
                         const uint32_t word = lds_ld(rowb + 4u * (uint32_t)(x / 8));
@@ -2042,7 +2107,7 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                     break;
                 }
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < HR; ++h) {
                     const int r = lane + 64 * h;
                     if (r < nch * B) {
                         const int cc = r / B, x = w0 + (r - cc * B);
@@ -2059,13 +2124,20 @@ __device__ __forceinline__ void run_ising_cstream(const ProbDev &p, const WorkIt
                             d0 += cr;
                             d1 += cr;
                         }
-                        CompactBulk fb;
-                        compact_cols(BulkDiff{cur[h], d0, d1}, fb);
-                        compact_steps(BulkDiff{cur[h], d0, d1}, fb);
                         const uint32_t slot = ring0 + (uint32_t)cc * RS + (uint32_t)(x % R) * RECB;
                         lds_st4(slot, uu[h]);
-                        lds_st4(slot + 16u, make_uint4(fb.a0, fb.a1, fb.e0, fb.e1));
-                        lds_st4(slot + 32u, make_uint4(fb.z0, fb.z1, 0u, 0u));
+                        if constexpr (COMPACT) {
+                            CompactBulk fb;
+                            compact_cols(BulkDiff{cur[h], d0, d1}, fb);
+                            compact_steps(BulkDiff{cur[h], d0, d1}, fb);
+                            lds_st4(slot + 16u, make_uint4(fb.a0, fb.a1, fb.e0, fb.e1));
+                            lds_st4(slot + 32u, make_uint4(fb.z0, fb.z1, 0u, 0u));
+                        } else {
+                            FastBulk fb;
+                            bulk_cols<false>(BulkDiff{cur[h], d0, d1}, fb);
+                            bulk_steps<false>(BulkDiff{cur[h], d0, d1}, fb);
+                            lds_st4(slot + 16u, make_uint4(fb.a0, fb.a1, fb.e0, fb.e1));
+                        }
                     }
                 }
                 // publish in order: after batch c - 1 (formed by the previous wave)
@@ -2094,8 +2166,12 @@ __device__ __forceinline__ bool run_fast_if_supported(const ProbDev &p, const Wo
                                                       const SweepLaunch &l, uint32_t sweep0, const LdsPlan &plan) {
     if constexpr (CS) {
         if (!MAG && stream_compact_ising(p, it)) {
-            if (p.L == 96) run_ising_cstream<96>(p, it, lds, l, sweep0, plan);
-            else run_ising_cstream<128>(p, it, lds, l, sweep0, plan);
+            if (p.L == 96) run_ising_cstream<96, true>(p, it, lds, l, sweep0, plan);
+            else run_ising_cstream<128, true>(p, it, lds, l, sweep0, plan);
+            return true;
+        }
+        if (!MAG && stream_bit_ising(p, it)) {
+            run_ising_cstream<64, false>(p, it, lds, l, sweep0, plan);
             return true;
         }
     }
@@ -2987,10 +3063,10 @@ __device__ __forceinline__ void run_item(const ProbDev &p, const WorkItem &it, c
     }
 }
 
-// One instantiation with the streamed compact Ising walker (CS) and one
-// without: the walker adds code that, compiled into the same kernel, slows
-// the other walkers by about 2 %, so launches without such items use the
-// kernel without it.
+// One instantiation with the streamed Ising walkers on bit lattices (CS) and
+// one without: their code, compiled into the same kernel, slows the other
+// walkers by about 2 %, so launches without such items use the kernel
+// without it.
 template <bool CS>
 __global__ void __launch_bounds__(64 * (1 + kMaxProducerWaves)) sweep_kernel(SweepLaunch l) {
     extern __shared__ __align__(16) char lds[];

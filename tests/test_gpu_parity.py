@@ -410,9 +410,9 @@ def test_multimagnetic_fast_walker_production(L):
 
 @pytest.mark.parametrize("chains,cw", [(100, 64), (40, 32)], ids=["c100-cw64", "c40-cw32"])
 def test_packed_l64_walker_bit_exact(chains, cw):
-    """Ising L = 64 with more than 16 chains per workgroup keeps the lattice as
-    bits and unpacks a ring of rows (with 32 + 8 chains one launch mixes the
-    packed and the byte layout): trajectories, histograms, weights, and
+    """Ising L = 64 with more than 16 chains per workgroup keeps the lattices as
+    bits (the streamed walker on bit lattices; with 32 + 8 chains one launch
+    mixes it with the byte walker): trajectories, histograms, weights, and
     production counts and |M| sums equal the oracle's."""
     pm = _pm()
     prob = Problem(ISING, 64, chains, 41 + chains)
@@ -447,8 +447,9 @@ def test_fast_walkers_long_launch_bit_exact(prob, n_sweeps, cw, rng_mode):
     of chunk hand-offs between the producer waves (which read the lattice one or
     two chunks ahead of the walker) and the walker, with one or three producer
     waves.  L = 16 has four chunks per sweep, the fewest the walkers allow; the
-    wide cases run the Potts walker with its small chunks and the packed Ising
-    L = 64 walker (each next to a narrow work item for the remaining chains).
+    wide cases run the Potts walker with its small chunks and the Ising L = 64
+    walker on bit lattices (each next to a narrow work item for the remaining
+    chains).
     Trajectories, per-chain histograms and energies equal the oracle's."""
     pm = _pm()
     print("case", prob, n_sweeps, cw, rng_mode, flush=True)
