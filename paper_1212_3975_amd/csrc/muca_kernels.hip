@@ -1762,16 +1762,18 @@ __device__ __forceinline__ void run_ising_packed(const ProbDev &p, const WorkIte
     }
 }
 
-// ------------------------------------------------------------------ streamed compact Ising walker
+// ------------------------------------------------------------------ streamed Ising walker on bit lattices
 //
-// The packed walker above unpacks rows, forms every dword's bulk and decodes
-// the compact table in one wave: about 139 cycles per site at L = 96 and 128.  Here,
-// as in the streamed Ising and Potts walkers, the helper waves form each
-// dword's complete record from the bit lattice once the walker has left the
-// row above (the draws' 14-bit prefixes, then column codes, row steps and
-// decode codes of both candidates), and the walker only decides sites and
-// xors each dword's flips, as a nibble, into the bit lattice.  Ties with the
-// 14-bit entries are redone exactly (redo_compact_dword).
+// The packed walker above unpacks rows, forms every dword's bulk and, at L =
+// 96 and 128, decodes the compact table in one wave: about 110 (L = 64) and
+// 139 (L = 96, 128) cycles per site.  Here, as in the streamed Ising and
+// Potts walkers, the helper waves form each dword's complete record from the
+// bit lattice once the walker has left the row above (the draws, or their
+// 14-bit prefixes on the compact table, then column codes, row steps and,
+// compact, decode codes of both candidates), and the walker only decides
+// sites and xors each dword's flips, as a nibble, into the bit lattice.  On
+// the compact table ties with the 14-bit entries are redone exactly
+// (redo_compact_dword).
 
 // The four sites of one dword: as walk_dword_pstream (compact decode, ties
 // folded a site later), with one flip bit per site: bit b0 + j for site j.
